@@ -1,0 +1,100 @@
+/*
+ * FP64 CPU oracle for one MUSCL-Hancock step of the HERACLES++ Godunov scheme.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, single-threaded
+ * reference that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product path never does.  It shares no code, header or table with the HIP
+ * library.
+ *
+ * Units of the paper followed here:
+ *   Sect. 2.1 (eqs. continuity, momentum, energy, passive scalar), Sect. 2.2
+ *   (uniform / point / enclosed-mass gravity), Sect. 2.3 (ideal-gas EoS),
+ *   Sect. 3.1.1 (mesh, dS, dV), Sect. 3.1.2 (spherical momentum sources,
+ *   eq. source_terms_1 and the theta counterpart), Sect. 3.2 (slope-limited
+ *   reconstruction, Hancock half step, Godunov update eq. godunov, HLL/HLLC,
+ *   boundary conditions).
+ *
+ * Pins (tests/test_oracle_*.py): limiters against closed forms and the TVD region; HLL/HLLC
+ * against consistency, exact contact resolution, mirror symmetry and the exact Godunov flux for
+ * weak waves; the whole step against the exact Sod solution (convergence), first-order Godunov by
+ * brute force, conservation, free stream, mirror/permutation symmetry, 1D data in 3D, free fall
+ * under uniform gravity, a static spherical wedge, discrete angular momentum, the closed-form
+ * enclosed mass and the Sedov-Taylor shock radius; the MLP against torch and finite differences.
+ */
+#ifndef HYDRO_ORACLE_H
+#define HYDRO_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_CART = 0, OR_SPH = 1 };
+enum { OR_HLL = 0, OR_HLLC = 1 };
+enum { OR_LIM_NONE = 0, OR_LIM_MINMOD = 1, OR_LIM_VANLEER = 2, OR_LIM_VANALBADA = 3, OR_LIM_MLP = 4 };
+enum { OR_BC_PERIODIC = 0, OR_BC_TRANSMISSIVE = 1, OR_BC_REFLECTIVE = 2 };
+enum { OR_GRAV_NONE = 0, OR_GRAV_UNIFORM = 1, OR_GRAV_POINT = 2, OR_GRAV_POINT_MONOPOLE = 3 };
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ENONPHYS = -3, OR_ENOMEM = -5 };
+
+#define OR_MLP_NPARAM 1249   /* 4*32+32 + 32*32+32 + 32+1 */
+
+typedef struct {
+    int ndim;                 /* 1..3 active axes (x1, x2, x3 in that order) */
+    int geom;                 /* OR_CART or OR_SPH */
+    int n[3];                 /* interior cells per axis (1 for inactive axes) */
+    int ng;                   /* ghost layers (2; 3 for the MLP limiter) */
+    const double *faces[3];   /* active: n+1+2ng faces incl. ghost faces; inactive: 2 faces */
+    int nscalar;
+    double gamma;
+    double cfl;
+    int riemann;
+    int limiter;
+    int bc[3][2];
+    int gravity;
+    double g0[3];
+    double G, Mc;
+    const double *mlp;        /* OR_MLP_NPARAM weights, W1[32][4] b1 W2[32][32] b2 w3[32] b3 */
+} or_config;
+
+/* Full step of interior U (layout [nvar][n3][n2][n1]) with time step dt into Unew.
+ * Returns OR_OK, or OR_ENONPHYS if any updated cell has rho<=0, p<=0 or a non-finite value
+ * (Unew is written in every case), or OR_EINVAL. */
+int or_step(const or_config *c, const double *U, double dt, double *Unew);
+
+/* Same step, evaluated only for the interior box [lo, hi) (per axis); out has the box's
+ * shape [nvar][hi2-lo2][hi1-lo1][hi0-lo0].  Used for sampled checks of large grids. */
+int or_step_box(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
+                double *out);
+
+/* CFL time step: dt = cfl / max over interior cells of sum_d (|u_d| + c_s)/dx_d. */
+int or_compute_dt(const or_config *c, const double *U, double *dt);
+
+/* Conserved totals sum_cells U_v dV, one per variable. */
+void or_totals(const or_config *c, const double *U, double *tot);
+
+/* Enclosed mass M_enc(r_i) per radial shell (spherical wedge, Sect. 2.2 eq. internal_gravity). */
+int or_enclosed_mass(const or_config *c, const double *U, double *menc);
+
+/* Single-interface Riemann flux in direction d for conserved states qL, qR (nvar each). */
+void or_riemann_flux(int solver, int d, int nvar, double gamma, const double *qL, const double *qR,
+                     double *flux);
+
+/* Half increment of a limited slope, limiter(a, b) (Sect. 3.2). */
+double or_limiter(int lim, double a, double b);
+
+/* MLP limiter network on one normalised stencil x[4]: returns phi in (0, 2). */
+double or_mlp_phi(const double *w, const double x[4]);
+
+/* MLP limited half increment for the undivided differences d[4] and geometric factors. */
+double or_mlp_slope(const double *w, const double d[4], double cm, double cp);
+
+/* Batched MLP forward + loss + gradient in FP64 (training, Sect. "learned limiter").
+ * x: [B][4] normalised inputs, a: [B] base (phi multiplies a), t: [B] target, wt: [B] weights.
+ * Loss L = sum_b wt_b (phi_b a_b - t_b)^2 / sum_b wt_b. grad: OR_MLP_NPARAM. Returns L. */
+double or_mlp_loss_grad(const double *w, int B, const double *x, const double *a, const double *t,
+                        const double *wt, double *grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
