@@ -1,0 +1,142 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) MUSCL-Hancock Godunov hydrodynamics step.
+ *
+ * The library advances the Euler equations with gravity and passive scalars (paper Sect. 2.1,
+ * eqs. continuity, momentum, energy, passive_scalar; Sect. 2.2 gravity; Sect. 2.3 ideal-gas EoS)
+ * by one time step of the unsplit MUSCL-Hancock scheme with HLL/HLLC fluxes (Sect. 3.2: slope-
+ * limited reconstruction, Hancock half step, Godunov update eq. godunov, boundary conditions),
+ * on Cartesian or spherical-wedge grids in 1D-3D (Sect. 3.1.1), including the spherical momentum
+ * source terms of Sect. 3.1.2 (eq. source_terms_1 and its theta counterpart).
+ *
+ * Data layout.  A state is nvar = 5 + nscalar fields, structure of arrays, x fastest:
+ *   U[v][k][j][i], v in (rho, rho u1, rho u2, rho u3, E, rho f_1 .. rho f_nscalar),
+ *   i < n[0], j < n[1], k < n[2]; interior cells only (ghost cells are never stored).
+ * In spherical geometry axis 0 is r, axis 1 theta, axis 2 phi, and (u1, u2, u3) = (u_r, u_theta,
+ * u_phi).  All three momentum components are carried in every dimension.
+ *
+ * Ownership.  The caller owns every device buffer and the stream: the workspace passed to
+ * hx_create, the state buffers passed to hx_set_state / hx_get_state and any device dt buffer.
+ * The library never allocates or frees device memory; it borrows the workspace and the stream
+ * until hx_destroy.  Host arrays (faces, weights) are copied during the call.
+ *
+ * Errors.  Every entry point returns a status; nothing aborts or prints.  HX_EHIP carries the HIP
+ * error text in hx_last_error() (thread-local).  A non-physical state (rho <= 0, p <= 0 or a
+ * non-finite value) is detected on the device while the state is read (by hx_step and
+ * hx_compute_dt*) and reported as HX_ENONPHYS by the next synchronising call (hx_compute_dt,
+ * hx_totals, hx_check); it stays reported until hx_set_state loads a new state.
+ *
+ * Threads and streams.  One context per stream; calls on one context must not overlap.
+ * All device work of a context is enqueued on its stream in call order.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hx_ctx hx_ctx;
+
+typedef enum {
+    HX_OK = 0,
+    HX_EINVAL = -1,    /* invalid configuration or argument */
+    HX_EHIP = -2,      /* a HIP runtime call failed */
+    HX_ENONPHYS = -3,  /* a non-physical state was met */
+    HX_ESTATE = -4,    /* call out of order (e.g. step before set_state, MLP without weights) */
+    HX_ENOSPACE = -5   /* workspace smaller than hx_workspace_bytes() */
+} hx_status;
+
+enum { HX_GEOM_CART = 0, HX_GEOM_SPH = 1 };
+enum { HX_RIEMANN_HLL = 0, HX_RIEMANN_HLLC = 1 };
+enum { HX_LIMITER_NONE = 0, HX_LIMITER_MINMOD = 1, HX_LIMITER_VANLEER = 2, HX_LIMITER_VANALBADA = 3,
+       HX_LIMITER_MLP = 4 };
+enum { HX_PRECISION_FP64 = 0, HX_PRECISION_FP32 = 1 };
+enum { HX_BOUNDARY_PERIODIC = 0, HX_BOUNDARY_TRANSMISSIVE = 1, HX_BOUNDARY_REFLECTIVE = 2 };
+enum { HX_GRAVITY_NONE = 0, HX_GRAVITY_UNIFORM = 1, HX_GRAVITY_POINT = 2, HX_GRAVITY_POINT_MONOPOLE = 3 };
+
+#define HX_MLP_NPARAM 1249 /* 4->32->32->1: W1[32][4] b1[32] W2[32][32] b2[32] w3[32] b3 */
+
+typedef struct {
+    int ndim;               /* 1, 2 or 3 active axes (axes 0..ndim-1) */
+    int geom;               /* HX_GEOM_*; spherical: axis 0 = r, 1 = theta, 2 = phi */
+    int n[3];               /* interior cells per axis; 1 on inactive axes; active axes >= nghost */
+    int nghost;             /* ghost layers: 2 (3 for HX_LIMITER_MLP) */
+    const double *faces[3]; /* host; active axis: n+1+2*nghost increasing face coordinates incl.
+                               ghost faces (a ghost cell's geometry); inactive axis: 2 faces */
+    int nscalar;            /* passive scalars, 0..4 */
+    double gamma;           /* adiabatic index (eq. eos_gas) */
+    double cfl;             /* Courant number of hx_compute_dt */
+    int riemann;            /* HX_RIEMANN_* (Sect. 3.2) */
+    int limiter;            /* HX_LIMITER_* (Sect. 3.2) */
+    int precision;          /* HX_PRECISION_*: FP64, or FP32 storage/bulk with FP64 energy
+                               recovery, time step, totals and source terms */
+    int bc[3][2];           /* HX_BOUNDARY_* per axis, low and high side (Sect. 3.2) */
+    int gravity;            /* HX_GRAVITY_*: uniform g0 (Cartesian, eq. uniform_gravity); point mass
+                               G*Mc (spherical, eq. point_gravity); point mass plus the enclosed
+                               mass of the wedge, scaled to the full sphere (eq. internal_gravity) */
+    double g0[3];
+    double G, Mc;
+} hx_config;
+
+/* Device bytes the caller must provide to hx_create for this configuration, or 0 if the
+ * configuration is invalid (hx_last_error says why). */
+size_t hx_workspace_bytes(const hx_config *cfg);
+
+/* Validate cfg, copy the grid, lay out the workspace (device, >= hx_workspace_bytes(cfg) bytes,
+ * 256-byte aligned) and bind the HIP stream (hipStream_t, may be NULL for the default stream).
+ * Enqueues the upload of the geometry tables on the stream. */
+hx_status hx_create(const hx_config *cfg, void *d_workspace, size_t workspace_bytes, void *hip_stream,
+                    hx_ctx **out);
+
+/* Load a state: d_U is a device FP64 array [nvar][n3][n2][n1].  The FP32 form rounds it to FP32.
+ * Clears the non-physical flag.  Asynchronous on the context's stream. */
+hx_status hx_set_state(hx_ctx *ctx, const double *d_U);
+
+/* Store the current state to the device FP64 array d_U (same layout; the FP32 form widens
+ * exactly).  Asynchronous. */
+hx_status hx_get_state(hx_ctx *ctx, double *d_U);
+
+/* CFL time step dt = cfl / max_cells sum_d (|u_d| + c_s) / dx_d over the current state (FP64),
+ * with dx_d the physical widths dr, r dtheta, r sin(theta) dphi.  Synchronises the stream;
+ * returns HX_ENONPHYS if a non-physical state was met since the last hx_set_state. */
+hx_status hx_compute_dt(hx_ctx *ctx, double *h_dt);
+
+/* Same time step written to the device double *d_dt; asynchronous, no check. */
+hx_status hx_compute_dt_device(hx_ctx *ctx, double *d_dt);
+
+/* Advance the current state by one step of length dt (host value).  Asynchronous. */
+hx_status hx_step(hx_ctx *ctx, double dt);
+
+/* Advance by one step whose length is read on the device from *d_dt (e.g. written by
+ * hx_compute_dt_device), so that a time loop needs no host synchronisation.  Asynchronous. */
+hx_status hx_step_device(hx_ctx *ctx, const double *d_dt);
+
+/* Conserved totals sum_cells U_v dV (FP64), nvar values to host h_tot.  Synchronises; returns
+ * HX_ENONPHYS like hx_compute_dt. */
+hx_status hx_totals(hx_ctx *ctx, double *h_tot);
+
+/* Synchronise the stream and report HX_ENONPHYS / HIP errors. */
+hx_status hx_check(hx_ctx *ctx);
+
+/* Weights of the learned slope limiter, HX_MLP_NPARAM FP32 values (host), layout as above. */
+hx_status hx_set_mlp(hx_ctx *ctx, const float *h_w, size_t n);
+
+/* Tuning: z planes per workgroup of the 3D sweep (default 32).  Does not change results. */
+hx_status hx_set_zchunk(hx_ctx *ctx, int kz);
+
+/* Enclosed-mass table of the last step that used HX_GRAVITY_POINT_MONOPOLE (n[0] doubles to the
+ * host; synchronises).  For tests of the enclosed-mass reduction. */
+hx_status hx_enclosed_mass(hx_ctx *ctx, double *h_menc);
+
+/* Thread-local text of the last error. */
+const char *hx_last_error(void);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+void hx_destroy(hx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,598 @@
+// C ABI of the gfx950 hydrodynamics step (see include/hydro.h for the contract).
+//
+// Host side only: validates the configuration, derives the per-axis geometry tables
+// (Sect. 3.1.1: cell centres, widths, dV and dS factors, computed in FP64 on the host),
+// lays out the caller's workspace and enqueues the kernels on the caller's stream.
+#include "hydro.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hx_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hx_status fail(hx_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHECK(call)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(HX_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));               \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_RED_BLOCKS = 2048;
+constexpr int MAX_SHELL_CHUNKS = 64;
+
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// image of index i on an axis of n cells (periodic / transmissive / reflective)
+int bc_map(int i, int n, int lo, int hi, bool& flip)
+{
+    flip = false;
+    if (i < 0) {
+        if (lo == HX_BOUNDARY_PERIODIC)
+            return i + n;
+        if (lo == HX_BOUNDARY_TRANSMISSIVE)
+            return 0;
+        flip = true;
+        return -1 - i;
+    }
+    if (i >= n) {
+        if (hi == HX_BOUNDARY_PERIODIC)
+            return i - n;
+        if (hi == HX_BOUNDARY_TRANSMISSIVE)
+            return n - 1;
+        flip = true;
+        return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+struct Layout {
+    size_t state[2];
+    size_t tab[3][3];  // cm, cp, w per axis
+    size_t rabs, sabs, rf, vr, hr, ct, sf;
+    size_t gr, menc, shell, partial, dt, flag, tot, mlp;
+    size_t total;
+    int ntab[3];
+    int nchunk, nred;
+};
+
+int nvar_of(const hx_config* c) { return 5 + c->nscalar; }
+
+long long ncells_of(const hx_config* c) { return (long long)c->n[0] * c->n[1] * c->n[2]; }
+
+hx_status validate(const hx_config* c)
+{
+    if (!c)
+        return fail(HX_EINVAL, "null configuration");
+    if (c->ndim < 1 || c->ndim > 3)
+        return fail(HX_EINVAL, "ndim must be 1, 2 or 3 (got %d)", c->ndim);
+    if (c->geom != HX_GEOM_CART && c->geom != HX_GEOM_SPH)
+        return fail(HX_EINVAL, "unknown geometry %d", c->geom);
+    if (c->nscalar < 0 || c->nscalar > 4)
+        return fail(HX_EINVAL, "nscalar must be 0..4 (got %d)", c->nscalar);
+    if (c->nghost != 2 && c->nghost != 3)
+        return fail(HX_EINVAL, "nghost must be 2 or 3 (got %d)", c->nghost);
+    if (c->limiter < HX_LIMITER_NONE || c->limiter > HX_LIMITER_MLP)
+        return fail(HX_EINVAL, "unknown limiter %d", c->limiter);
+    if (c->limiter == HX_LIMITER_MLP)
+        return fail(HX_EINVAL, "the learned limiter is not available in this build");
+    if (c->riemann != HX_RIEMANN_HLL && c->riemann != HX_RIEMANN_HLLC)
+        return fail(HX_EINVAL, "unknown Riemann solver %d", c->riemann);
+    if (c->precision != HX_PRECISION_FP64 && c->precision != HX_PRECISION_FP32)
+        return fail(HX_EINVAL, "unknown precision %d", c->precision);
+    if (!(c->gamma > 1.0) || !(c->cfl > 0.0))
+        return fail(HX_EINVAL, "need gamma > 1 and cfl > 0");
+    for (int d = 0; d < 3; d++) {
+        const bool act = d < c->ndim;
+        if (act && c->n[d] < c->nghost)
+            return fail(HX_EINVAL, "axis %d: %d cells, need at least nghost = %d", d, c->n[d], c->nghost);
+        if (!act && c->n[d] != 1)
+            return fail(HX_EINVAL, "inactive axis %d must have n = 1", d);
+        if (!c->faces[d])
+            return fail(HX_EINVAL, "faces of axis %d missing", d);
+        const int nf = act ? c->n[d] + 1 + 2 * c->nghost : 2;
+        for (int f = 1; f < nf; f++)
+            if (!(c->faces[d][f] > c->faces[d][f - 1]))
+                return fail(HX_EINVAL, "faces of axis %d must increase (index %d)", d, f);
+        for (int s = 0; s < 2; s++)
+            if (c->bc[d][s] < 0 || c->bc[d][s] > 2)
+                return fail(HX_EINVAL, "unknown boundary %d on axis %d", c->bc[d][s], d);
+        if (act && ((c->bc[d][0] == HX_BOUNDARY_PERIODIC) != (c->bc[d][1] == HX_BOUNDARY_PERIODIC)))
+            return fail(HX_EINVAL, "axis %d: periodic boundaries must be periodic on both sides", d);
+    }
+    if (c->ndim == 3 && c->n[0] > 1 << 20)
+        return fail(HX_EINVAL, "axis 0 too long");
+    if (c->gravity < HX_GRAVITY_NONE || c->gravity > HX_GRAVITY_POINT_MONOPOLE)
+        return fail(HX_EINVAL, "unknown gravity %d", c->gravity);
+    if (c->gravity == HX_GRAVITY_UNIFORM && c->geom != HX_GEOM_CART)
+        return fail(HX_EINVAL, "uniform gravity needs Cartesian geometry");
+    if ((c->gravity == HX_GRAVITY_POINT || c->gravity == HX_GRAVITY_POINT_MONOPOLE) && c->geom != HX_GEOM_SPH)
+        return fail(HX_EINVAL, "point-mass gravity needs spherical geometry");
+    if (c->gravity == HX_GRAVITY_POINT_MONOPOLE && c->n[0] > HX_MAX_NR)
+        return fail(HX_EINVAL, "enclosed-mass gravity supports at most %d radial cells", HX_MAX_NR);
+    if (c->geom == HX_GEOM_SPH) {
+        const double r0 = c->faces[0][c->nghost];
+        if (r0 < 0.0 || (r0 == 0.0 && c->bc[0][0] != HX_BOUNDARY_REFLECTIVE))
+            return fail(HX_EINVAL, "spherical grid: r must be positive (r = 0 needs a reflective centre)");
+        const double* th = c->faces[1];
+        const int o = c->ndim >= 2 ? c->nghost : 0;
+        const double t0 = th[o], t1 = th[o + c->n[1]];
+        if (t0 < 0.0 || t1 > M_PI + 1e-12)
+            return fail(HX_EINVAL, "spherical grid: theta must lie in [0, pi]");
+    }
+    return HX_OK;
+}
+
+Layout layout(const hx_config* c)
+{
+    Layout L;
+    const int nv = nvar_of(c);
+    const long long nc = ncells_of(c);
+    const size_t rb = c->precision == HX_PRECISION_FP32 ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += up(bytes);
+        return o;
+    };
+    L.state[0] = take(rb * nv * nc);
+    L.state[1] = take(rb * nv * nc);
+    for (int d = 0; d < 3; d++) {
+        L.ntab[d] = d < c->ndim ? c->n[d] + 2 * c->nghost : 1;
+        for (int t = 0; t < 3; t++)
+            L.tab[d][t] = take(sizeof(double) * L.ntab[d]);
+    }
+    L.rabs = take(sizeof(double) * L.ntab[0]);
+    L.sabs = take(sizeof(double) * L.ntab[1]);
+    L.rf = take(sizeof(double) * (c->n[0] + 1));
+    L.vr = take(sizeof(double) * c->n[0]);
+    L.hr = take(sizeof(double) * c->n[0]);
+    L.ct = take(sizeof(double) * c->n[1]);
+    L.sf = take(sizeof(double) * (c->n[1] + 1));
+    L.gr = take(sizeof(double) * c->n[0]);
+    L.menc = take(sizeof(double) * c->n[0]);
+    long long rows = (long long)c->n[1] * c->n[2];
+    L.nchunk = (int)(rows < MAX_SHELL_CHUNKS ? rows : MAX_SHELL_CHUNKS);
+    L.shell = take(sizeof(double) * (size_t)L.nchunk * c->n[0]);
+    long long nb = (nc + 255) / 256;
+    L.nred = (int)(nb < MAX_RED_BLOCKS ? nb : MAX_RED_BLOCKS);
+    L.partial = take(sizeof(double) * (size_t)L.nred * (nv > 1 ? nv : 1));
+    L.dt = take(sizeof(double));
+    L.flag = take(sizeof(int));
+    L.tot = take(sizeof(double) * nv);
+    L.mlp = take(sizeof(float) * HX_MLP_NPARAM);
+    L.total = off;
+    return L;
+}
+
+__global__ void clear_flag_kernel(int* f) { f[0] = 0; }
+
+}  // namespace
+
+struct hx_ctx {
+    hx_config cfg;
+    std::vector<double> faces[3];
+    std::vector<double> host_tabs;  // staging of the geometry upload (kept alive for the async copy)
+    int nvar = 0, ng = 0;
+    long long ncells = 0;
+    bool fp32 = false;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L;
+    void* state[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool have_state = false;
+    bool have_mlp = false;
+    hx::Geo geo;
+    int kz = 32;
+    double scale = 0.0;  // 4 pi / Omega_w
+};
+
+namespace {
+
+template <typename T>
+T* at(hx_ctx* c, size_t off)
+{
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+// geometry of the oracle's definitions, computed once on the host in FP64
+void build_geometry(hx_ctx* x, std::vector<double>& h, std::vector<std::pair<size_t, size_t>>& spans)
+{
+    const hx_config& c = x->cfg;
+    const int ng = c.nghost;
+    auto xf = [&](int d, int i) { return d < c.ndim ? x->faces[d][i + ng] : x->faces[d][i]; };
+    auto xcen = [&](int d, int i) { return 0.5 * (xf(d, i) + xf(d, i + 1)); };
+    auto dxc = [&](int d, int i) { return xf(d, i + 1) - xf(d, i); };
+    auto push = [&](size_t off, const std::vector<double>& v) {
+        spans.push_back({off, h.size()});
+        h.insert(h.end(), v.begin(), v.end());
+    };
+    for (int d = 0; d < 3; d++) {
+        const bool act = d < c.ndim;
+        const int nt = x->L.ntab[d];
+        std::vector<double> cm(nt, 0.5), cp(nt, 0.5), w(nt, 0.0);
+        for (int t = 0; t < nt; t++) {
+            const int i = act ? t - ng : 0;
+            bool fl;
+            const int im = act ? bc_map(i, c.n[d], c.bc[d][0], c.bc[d][1], fl) : 0;
+            w[t] = dxc(d, im);
+            if (act && i - 1 >= -ng && i + 1 <= c.n[d] + ng - 1) {
+                const double half = 0.5 * dxc(d, i);
+                cm[t] = half / (xcen(d, i) - xcen(d, i - 1));
+                cp[t] = half / (xcen(d, i + 1) - xcen(d, i));
+            }
+        }
+        push(x->L.tab[d][0], cm);
+        push(x->L.tab[d][1], cp);
+        push(x->L.tab[d][2], w);
+    }
+    {
+        const int nt = x->L.ntab[0];
+        std::vector<double> rabs(nt);
+        for (int t = 0; t < nt; t++) {
+            bool fl;
+            const int im = bc_map(t - ng, c.n[0], c.bc[0][0], c.bc[0][1], fl);
+            rabs[t] = std::fabs(xcen(0, im));
+        }
+        push(x->L.rabs, rabs);
+    }
+    {
+        const int nt = x->L.ntab[1];
+        const bool act = c.ndim >= 2;
+        std::vector<double> sabs(nt);
+        for (int t = 0; t < nt; t++) {
+            bool fl;
+            const int im = act ? bc_map(t - ng, c.n[1], c.bc[1][0], c.bc[1][1], fl) : 0;
+            sabs[t] = std::fabs(std::sin(xcen(1, im)));
+        }
+        push(x->L.sabs, sabs);
+    }
+    const int n0 = c.n[0], n1 = c.n[1];
+    std::vector<double> rf(n0 + 1), vr(n0), hr(n0), ct(n1), sf(n1 + 1);
+    for (int i = 0; i <= n0; i++)
+        rf[i] = xf(0, i);
+    for (int i = 0; i < n0; i++) {
+        const double rm = xf(0, i), rp = xf(0, i + 1);
+        vr[i] = (rp * rp * rp - rm * rm * rm) / 3.0;
+        hr[i] = 0.5 * (rp * rp - rm * rm);
+    }
+    for (int j = 0; j < n1; j++)
+        ct[j] = std::cos(xf(1, j)) - std::cos(xf(1, j + 1));
+    for (int j = 0; j <= n1; j++)
+        sf[j] = std::sin(xf(1, j));
+    push(x->L.rf, rf);
+    push(x->L.vr, vr);
+    push(x->L.hr, hr);
+    push(x->L.ct, ct);
+    push(x->L.sf, sf);
+    // solid angle of the wedge and point-mass gravity (the monopole part is recomputed per step)
+    double om_t = 0.0, om_p = 0.0;
+    for (int j = 0; j < n1; j++)
+        om_t += ct[j];
+    for (int k = 0; k < c.n[2]; k++)
+        om_p += dxc(2, k);
+    x->scale = 4.0 * M_PI / (om_t * om_p);
+    std::vector<double> gr(n0, 0.0);
+    if (c.gravity == HX_GRAVITY_POINT || c.gravity == HX_GRAVITY_POINT_MONOPOLE) {
+        for (int i = 0; i < n0; i++) {
+            const double rc = xcen(0, i);
+            gr[i] = -(c.G * (c.Mc + 0.0)) / (rc * rc);
+        }
+    }
+    push(x->L.gr, gr);
+}
+
+hx::Geo geo_of(hx_ctx* x)
+{
+    hx::Geo g;
+    for (int d = 0; d < 3; d++) {
+        g.cm[d] = at<double>(x, x->L.tab[d][0]);
+        g.cp[d] = at<double>(x, x->L.tab[d][1]);
+        g.w[d] = at<double>(x, x->L.tab[d][2]);
+    }
+    g.rabs = at<double>(x, x->L.rabs);
+    g.sabs = at<double>(x, x->L.sabs);
+    g.rf = at<double>(x, x->L.rf);
+    g.vr = at<double>(x, x->L.vr);
+    g.hr = at<double>(x, x->L.hr);
+    g.ct = at<double>(x, x->L.ct);
+    g.sf = at<double>(x, x->L.sf);
+    return g;
+}
+
+hx::DtParams dt_params(hx_ctx* x)
+{
+    hx::DtParams p;
+    p.U = x->state[x->cur];
+    for (int d = 0; d < 3; d++)
+        p.n[d] = x->cfg.n[d];
+    p.ng = x->ng;
+    p.ndim = x->cfg.ndim;
+    p.geom = x->cfg.geom;
+    p.nvar = x->nvar;
+    p.plane = x->ncells;
+    p.gamma = x->cfg.gamma;
+    p.gm1 = x->cfg.gamma - 1.0;
+    p.geo = x->geo;
+    p.partial = at<double>(x, x->L.partial);
+    p.flag = at<int>(x, x->L.flag);
+    return p;
+}
+
+hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
+{
+    if (!x->have_state)
+        return fail(HX_ESTATE, "step before set_state");
+    const hx_config& c = x->cfg;
+    if (c.gravity == HX_GRAVITY_POINT_MONOPOLE) {
+        hx::ShellParams s;
+        s.U = x->state[x->cur];
+        for (int d = 0; d < 3; d++)
+            s.n[d] = c.n[d];
+        s.ng = x->ng;
+        s.ndim = c.ndim;
+        s.geo = x->geo;
+        s.partial = at<double>(x, x->L.shell);
+        s.gr = at<double>(x, x->L.gr);
+        s.menc = at<double>(x, x->L.menc);
+        s.scale = x->scale;
+        s.G = c.G;
+        s.Mc = c.Mc;
+        HIPCHECK(hx::launch_shell(s, x->fp32, x->L.nchunk, x->stream));
+    }
+    hx::SweepParams p;
+    p.U = x->state[x->cur];
+    p.Unew = x->state[1 - x->cur];
+    for (int d = 0; d < 3; d++) {
+        p.n[d] = c.n[d];
+        p.bc[d][0] = c.bc[d][0];
+        p.bc[d][1] = c.bc[d][1];
+        p.g0[d] = c.g0[d];
+    }
+    p.ng = x->ng;
+    p.plane = x->ncells;
+    p.gamma = c.gamma;
+    p.dt_host = dt;
+    p.dt_dev = d_dt;
+    p.limiter = c.limiter;
+    p.riemann = c.riemann;
+    p.gravity = c.gravity;
+    p.gr = at<double>(x, x->L.gr);
+    p.geo = x->geo;
+    p.flag = at<int>(x, x->L.flag);
+    p.kz = c.ndim == 3 ? (x->kz < c.n[2] ? x->kz : c.n[2]) : 1;
+    p.mlp = at<float>(x, x->L.mlp);
+    hipError_t e = x->fp32 ? hx::launch_sweep_fp32(p, c.ndim, x->nvar, c.geom, x->stream)
+                           : hx::launch_sweep_fp64(p, c.ndim, x->nvar, c.geom, x->stream);
+    if (e != hipSuccess)
+        return fail(HX_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
+    x->cur = 1 - x->cur;
+    return HX_OK;
+}
+
+hx_status sync_check(hx_ctx* x)
+{
+    int flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, at<int>(x, x->L.flag), sizeof(int), hipMemcpyDeviceToHost, x->stream));
+    HIPCHECK(hipStreamSynchronize(x->stream));
+    if (flag)
+        return fail(HX_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or non-finite) met");
+    return HX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hx_workspace_bytes(const hx_config* cfg)
+{
+    if (validate(cfg) != HX_OK)
+        return 0;
+    return layout(cfg).total;
+}
+
+hx_status hx_create(const hx_config* cfg, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                    hx_ctx** out)
+{
+    if (!out)
+        return fail(HX_EINVAL, "null output pointer");
+    *out = nullptr;
+    hx_status st = validate(cfg);
+    if (st != HX_OK)
+        return st;
+    Layout L = layout(cfg);
+    if (!d_workspace || workspace_bytes < L.total)
+        return fail(HX_ENOSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(d_workspace) % ALIGN)
+        return fail(HX_EINVAL, "workspace must be %zu-byte aligned", ALIGN);
+    hx_ctx* x = new (std::nothrow) hx_ctx();
+    if (!x)
+        return fail(HX_EINVAL, "out of host memory");
+    x->cfg = *cfg;
+    x->ng = cfg->nghost;
+    x->nvar = nvar_of(cfg);
+    x->ncells = ncells_of(cfg);
+    x->fp32 = cfg->precision == HX_PRECISION_FP32;
+    x->stream = (hipStream_t)hip_stream;
+    x->ws = (char*)d_workspace;
+    x->L = L;
+    for (int d = 0; d < 3; d++) {
+        const int nf = d < cfg->ndim ? cfg->n[d] + 1 + 2 * cfg->nghost : 2;
+        x->faces[d].assign(cfg->faces[d], cfg->faces[d] + nf);
+        x->cfg.faces[d] = nullptr;
+    }
+    x->state[0] = x->ws + L.state[0];
+    x->state[1] = x->ws + L.state[1];
+    x->geo = geo_of(x);
+    std::vector<std::pair<size_t, size_t>> spans;
+    build_geometry(x, x->host_tabs, spans);
+    for (size_t s = 0; s < spans.size(); s++) {
+        const size_t beg = spans[s].second;
+        const size_t end = s + 1 < spans.size() ? spans[s + 1].second : x->host_tabs.size();
+        hipError_t e = hipMemcpyAsync(x->ws + spans[s].first, x->host_tabs.data() + beg,
+                                      sizeof(double) * (end - beg), hipMemcpyHostToDevice, x->stream);
+        if (e != hipSuccess) {
+            delete x;
+            return fail(HX_EHIP, "geometry upload failed: %s", hipGetErrorString(e));
+        }
+    }
+    clear_flag_kernel<<<1, 1, 0, x->stream>>>(at<int>(x, L.flag));
+    hipError_t e = hipStreamSynchronize(x->stream);
+    if (e != hipSuccess) {
+        delete x;
+        return fail(HX_EHIP, "create: %s", hipGetErrorString(e));
+    }
+    *out = x;
+    return HX_OK;
+}
+
+hx_status hx_set_state(hx_ctx* x, const double* d_U)
+{
+    if (!x || !d_U)
+        return fail(HX_EINVAL, "null argument");
+    const long long n = (long long)x->nvar * x->ncells;
+    if (x->fp32) {
+        HIPCHECK(hx::launch_convert(d_U, x->state[0], n, true, x->stream));
+    } else {
+        HIPCHECK(hipMemcpyAsync(x->state[0], d_U, sizeof(double) * n, hipMemcpyDeviceToDevice, x->stream));
+    }
+    x->cur = 0;
+    x->have_state = true;
+    clear_flag_kernel<<<1, 1, 0, x->stream>>>(at<int>(x, x->L.flag));
+    HIPCHECK(hipGetLastError());
+    return HX_OK;
+}
+
+hx_status hx_get_state(hx_ctx* x, double* d_U)
+{
+    if (!x || !d_U)
+        return fail(HX_EINVAL, "null argument");
+    if (!x->have_state)
+        return fail(HX_ESTATE, "no state loaded");
+    const long long n = (long long)x->nvar * x->ncells;
+    if (x->fp32) {
+        HIPCHECK(hx::launch_convert(x->state[x->cur], d_U, n, false, x->stream));
+    } else {
+        HIPCHECK(hipMemcpyAsync(d_U, x->state[x->cur], sizeof(double) * n, hipMemcpyDeviceToDevice, x->stream));
+    }
+    return HX_OK;
+}
+
+hx_status hx_compute_dt_device(hx_ctx* x, double* d_dt)
+{
+    if (!x || !d_dt)
+        return fail(HX_EINVAL, "null argument");
+    if (!x->have_state)
+        return fail(HX_ESTATE, "no state loaded");
+    hx::DtParams p = dt_params(x);
+    HIPCHECK(hx::launch_dt(p, x->fp32, x->L.nred, x->cfg.cfl, d_dt, x->stream));
+    return HX_OK;
+}
+
+hx_status hx_compute_dt(hx_ctx* x, double* h_dt)
+{
+    if (!x || !h_dt)
+        return fail(HX_EINVAL, "null argument");
+    hx_status st = hx_compute_dt_device(x, at<double>(x, x->L.dt));
+    if (st != HX_OK)
+        return st;
+    HIPCHECK(hipMemcpyAsync(h_dt, at<double>(x, x->L.dt), sizeof(double), hipMemcpyDeviceToHost, x->stream));
+    return sync_check(x);
+}
+
+hx_status hx_step(hx_ctx* x, double dt)
+{
+    if (!x)
+        return fail(HX_EINVAL, "null context");
+    if (!(dt > 0.0) || !std::isfinite(dt))
+        return fail(HX_EINVAL, "dt must be positive and finite");
+    return enqueue_step(x, dt, nullptr);
+}
+
+hx_status hx_step_device(hx_ctx* x, const double* d_dt)
+{
+    if (!x || !d_dt)
+        return fail(HX_EINVAL, "null argument");
+    return enqueue_step(x, 0.0, d_dt);
+}
+
+hx_status hx_totals(hx_ctx* x, double* h_tot)
+{
+    if (!x || !h_tot)
+        return fail(HX_EINVAL, "null argument");
+    if (!x->have_state)
+        return fail(HX_ESTATE, "no state loaded");
+    hx::DtParams p = dt_params(x);
+    HIPCHECK(hx::launch_totals(p, x->fp32, x->L.nred, at<double>(x, x->L.tot), x->stream));
+    HIPCHECK(hipMemcpyAsync(h_tot, at<double>(x, x->L.tot), sizeof(double) * x->nvar, hipMemcpyDeviceToHost,
+                            x->stream));
+    return sync_check(x);
+}
+
+hx_status hx_check(hx_ctx* x)
+{
+    if (!x)
+        return fail(HX_EINVAL, "null context");
+    return sync_check(x);
+}
+
+hx_status hx_set_mlp(hx_ctx* x, const float* h_w, size_t n)
+{
+    if (!x || !h_w)
+        return fail(HX_EINVAL, "null argument");
+    if (n != HX_MLP_NPARAM)
+        return fail(HX_EINVAL, "expected %d weights, got %zu", HX_MLP_NPARAM, n);
+    HIPCHECK(hipMemcpyAsync(at<float>(x, x->L.mlp), h_w, sizeof(float) * n, hipMemcpyHostToDevice, x->stream));
+    HIPCHECK(hipStreamSynchronize(x->stream));
+    x->have_mlp = true;
+    return HX_OK;
+}
+
+hx_status hx_set_zchunk(hx_ctx* x, int kz)
+{
+    if (!x || kz < 1)
+        return fail(HX_EINVAL, "z chunk must be >= 1");
+    x->kz = kz;
+    return HX_OK;
+}
+
+hx_status hx_enclosed_mass(hx_ctx* x, double* h_menc)
+{
+    if (!x || !h_menc)
+        return fail(HX_EINVAL, "null argument");
+    if (x->cfg.gravity != HX_GRAVITY_POINT_MONOPOLE)
+        return fail(HX_ESTATE, "no enclosed-mass gravity in this configuration");
+    HIPCHECK(hipMemcpyAsync(h_menc, at<double>(x, x->L.menc), sizeof(double) * x->cfg.n[0], hipMemcpyDeviceToHost,
+                            x->stream));
+    HIPCHECK(hipStreamSynchronize(x->stream));
+    return HX_OK;
+}
+
+const char* hx_last_error(void) { return g_err.c_str(); }
+
+void hx_destroy(hx_ctx* x) { delete x; }
+
+}  // extern "C"

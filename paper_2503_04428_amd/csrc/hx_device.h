@@ -1,0 +1,243 @@
+// Device-side numerics of the MUSCL-Hancock step for gfx950 (HIP).
+//
+// Conserved state U = (rho, m1, m2, m3, E, rho f_1..), primitives W = (rho, u1, u2, u3, P, f..)
+// (paper Sect. 2.1 and eq. eos_gas).  The FP64 instantiation evaluates every expression in the
+// same order as the FP64 CPU oracle so that the two agree to the last bits; the FP32 form keeps
+// the internal-energy recovery E - |m|^2/(2 rho) in FP64 and uses hardware reciprocal/sqrt.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hx_params.h"
+
+namespace hx {
+
+template <typename R>
+struct Num;
+
+template <>
+struct Num<double> {
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
+    static __device__ __forceinline__ double abs_(double a) { return fabs(a); }
+    static __device__ __forceinline__ double from_d(double a) { return a; }
+};
+
+template <>
+struct Num<float> {
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float sqrt_(float a) { return __builtin_amdgcn_sqrtf(a); }
+    static __device__ __forceinline__ float abs_(float a) { return fabsf(a); }
+    static __device__ __forceinline__ float from_d(double a) { return (float)a; }
+};
+
+template <typename R>
+struct Gas {
+    R gm1, inv_gm1, gamma;
+};
+
+// ---------------------------------------------------------------- EoS
+
+// primitives from conserved
+template <typename R, int NV>
+struct PrimImpl;
+
+template <int NV>
+struct PrimImpl<double, NV> {
+    static __device__ __forceinline__ void run(const Gas<double>& g, const double* q, double* w)
+    {
+        double rho = q[0];
+        double inv = 1.0 / rho;
+        double u1 = q[1] * inv, u2 = q[2] * inv, u3 = q[3] * inv;
+        double ke = 0.5 * (q[1] * u1 + q[2] * u2 + q[3] * u3);
+        w[0] = rho;
+        w[1] = u1;
+        w[2] = u2;
+        w[3] = u3;
+        w[4] = g.gm1 * (q[4] - ke);
+#pragma unroll
+        for (int v = 5; v < NV; v++)
+            w[v] = q[v] * inv;
+    }
+};
+
+template <int NV>
+struct PrimImpl<float, NV> {
+    // FP32 bulk, FP64 island for the internal energy: 1/rho from the hardware reciprocal refined
+    // by one FP64 Newton step, then e = E - |m|^2/(2 rho) in FP64.
+    static __device__ __forceinline__ void run(const Gas<float>& g, const float* q, float* w)
+    {
+        float rho = q[0];
+        float r = __builtin_amdgcn_rcpf(rho);
+        double id = (double)r;
+        id = id * (2.0 - (double)rho * id);
+        double m1 = q[1], m2 = q[2], m3 = q[3];
+        double ke = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * id;
+        float inv = (float)id;
+        w[0] = rho;
+        w[1] = q[1] * inv;
+        w[2] = q[2] * inv;
+        w[3] = q[3] * inv;
+        w[4] = (float)((double)g.gm1 * ((double)q[4] - ke));
+#pragma unroll
+        for (int v = 5; v < NV; v++)
+            w[v] = q[v] * inv;
+    }
+};
+
+template <typename R, int NV>
+__device__ __forceinline__ void to_prim(const Gas<R>& g, const R* q, R* w)
+{
+    PrimImpl<R, NV>::run(g, q, w);
+}
+
+template <typename R, int NV>
+__device__ __forceinline__ void to_cons(const Gas<R>& g, const R* w, R* q)
+{
+    R rho = w[0];
+    q[0] = rho;
+    q[1] = rho * w[1];
+    q[2] = rho * w[2];
+    q[3] = rho * w[3];
+    q[4] = w[4] * g.inv_gm1 + R(0.5) * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+#pragma unroll
+    for (int v = 5; v < NV; v++)
+        q[v] = rho * w[v];
+}
+
+// physical flux along axis D from primitives w and conserved q of the same state
+template <typename R, int NV, int D>
+__device__ __forceinline__ void phys_flux(const R* w, const R* q, R* f)
+{
+    R un = w[1 + D];
+    R mn = q[1 + D];
+    f[0] = mn;
+    f[1] = mn * w[1];
+    f[2] = mn * w[2];
+    f[3] = mn * w[3];
+    f[1 + D] = f[1 + D] + w[4];
+    f[4] = un * (q[4] + w[4]);
+#pragma unroll
+    for (int v = 5; v < NV; v++)
+        f[v] = mn * w[v];
+}
+
+// HLL / HLLC with Davis wave speeds (Sect. 3.2; textbook solvers the paper cites)
+template <typename R, int NV, int D>
+__device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL, const R* qR, R* F)
+{
+    using N = Num<R>;
+    R wL[NV], wR[NV], fL[NV], fR[NV];
+    to_prim<R, NV>(g, qL, wL);
+    to_prim<R, NV>(g, qR, wR);
+    phys_flux<R, NV, D>(wL, qL, fL);
+    phys_flux<R, NV, D>(wR, qR, fR);
+    R rL = wL[0], rR = wR[0];
+    R uL = wL[1 + D], uR = wR[1 + D];
+    R pL = wL[4], pR = wR[4];
+    R cL = N::sqrt_(N::div(g.gamma * pL, rL));
+    R cR = N::sqrt_(N::div(g.gamma * pR, rR));
+    R SL = fmin(uL - cL, uR - cR);
+    R SR = fmax(uL + cL, uR + cR);
+    if (SL >= R(0)) {
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            F[v] = fL[v];
+        return;
+    }
+    if (solver == HX_HLL) {
+        if (SR <= R(0)) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                F[v] = fR[v];
+            return;
+        }
+        R inv = N::div(R(1), SR - SL);
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            F[v] = (SR * fL[v] - SL * fR[v] + SL * SR * (qR[v] - qL[v])) * inv;
+        return;
+    }
+    R mL = rL * (SL - uL);
+    R mR = rR * (SR - uR);
+    R Ss = N::div(pR - pL + uL * mL - uR * mR, mL - mR);
+    if (!(Ss >= R(0)) && !(SR > R(0))) {
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            F[v] = fR[v];
+        return;
+    }
+    const bool left = Ss >= R(0);
+    R S = left ? SL : SR;
+    R m = left ? mL : mR;
+    R us[NV];
+    // select the star side through registers (no pointer selects, everything stays in VGPRs)
+    R qs[NV], ws[NV], fs[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        qs[v] = left ? qL[v] : qR[v];
+        ws[v] = left ? wL[v] : wR[v];
+        fs[v] = left ? fL[v] : fR[v];
+    }
+    R un = ws[1 + D];
+    R fac = N::div(m, S - Ss);
+    us[0] = fac;
+    us[1] = fac * ws[1];
+    us[2] = fac * ws[2];
+    us[3] = fac * ws[3];
+    us[1 + D] = fac * Ss;
+    us[4] = fac * (N::div(qs[4], ws[0]) + (Ss - un) * (Ss + N::div(ws[4], m)));
+#pragma unroll
+    for (int v = 5; v < NV; v++)
+        us[v] = fac * ws[v];
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+        F[v] = fs[v] + S * (us[v] - qs[v]);
+}
+
+template <typename R>
+__device__ __forceinline__ R limit(int lim, R a, R b)
+{
+    using N = Num<R>;
+    if (lim == HX_LIM_NONE)
+        return R(0);
+    if (!(a * b > R(0)))
+        return R(0);
+    if (lim == HX_LIM_MINMOD)
+        return N::abs_(a) < N::abs_(b) ? a : b;
+    if (lim == HX_LIM_VANALBADA)
+        return N::div(a * b * (a + b), a * a + b * b);
+    return N::div(R(2) * a * b, a + b);
+}
+
+// boundary image of index i on an axis with n cells; indices are first clamped into the
+// ghost range so that threads of ragged tiles always read inside the array
+__device__ __forceinline__ int bc_image(int i, int n, int ng, int lo, int hi, bool& flip)
+{
+    i = i < -ng ? -ng : (i > n + ng - 1 ? n + ng - 1 : i);
+    flip = false;
+    if (i < 0) {
+        if (lo == HX_BC_PERIODIC)
+            return i + n;
+        if (lo == HX_BC_TRANSMISSIVE)
+            return 0;
+        flip = true;
+        return -1 - i;
+    }
+    if (i >= n) {
+        if (hi == HX_BC_PERIODIC)
+            return i - n;
+        if (hi == HX_BC_TRANSMISSIVE)
+            return n - 1;
+        flip = true;
+        return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+__device__ __forceinline__ int clamp_ghost(int i, int n, int ng)
+{
+    return i < -ng ? -ng : (i > n + ng - 1 ? n + ng - 1 : i);
+}
+
+}  // namespace hx

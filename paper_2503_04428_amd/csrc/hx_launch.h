@@ -1,0 +1,56 @@
+// Host-side launch interface between the C ABI and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hx_params.h"
+
+#define HX_MAX_NR 4096   // radial shells supported by the enclosed-mass kernel
+
+namespace hx {
+
+struct DtParams {
+    const void* U;
+    int n[3];
+    int ng;
+    int ndim;
+    int geom;
+    int nvar;
+    long long plane;
+    double gamma, gm1;
+    Geo geo;
+    double* partial;
+    int* flag;
+};
+
+struct ShellParams {
+    const void* U;       // density field (first variable of the state)
+    int n[3];
+    int ng;
+    int ndim;
+    Geo geo;
+    double* partial;     // [nchunk][n0]
+    double* gr;          // out: radial acceleration per shell
+    double* menc;        // optional out: enclosed mass per shell
+    double scale;        // 4 pi / Omega_w
+    double G, Mc;
+};
+
+hipError_t launch_sweep_fp64(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_sweep_fp32(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_dt(const DtParams& p, bool fp32, int nblocks, double cfl, double* dt_out, hipStream_t s);
+hipError_t launch_totals(const DtParams& p, bool fp32, int nblocks, double* out, hipStream_t s);
+hipError_t launch_shell(const ShellParams& p, bool fp32, int nchunk, hipStream_t s);
+hipError_t launch_convert(const void* src, void* dst, long long n, bool to_f32, hipStream_t s);
+
+// grid of the fused sweep for a given shape
+inline dim3 sweep_grid(int ndim, const int n[3], int kz)
+{
+    if (ndim == 1)
+        return dim3((n[0] + 61) / 62, 1, 1);
+    if (ndim == 2)
+        return dim3((n[0] + 13) / 14, (n[1] + 13) / 14, 1);
+    return dim3((n[0] + 13) / 14, (n[1] + 13) / 14, (n[2] + kz - 1) / kz);
+}
+inline dim3 sweep_block(int ndim) { return ndim == 1 ? dim3(64, 1, 1) : dim3(16, 16, 1); }
+
+}  // namespace hx

@@ -1,0 +1,67 @@
+// Kernel parameter blocks and enums shared by the library's host launchers and its kernels.
+#pragma once
+#include <stdint.h>
+
+#define HX_CART 0
+#define HX_SPH 1
+#define HX_HLL 0
+#define HX_HLLC 1
+#define HX_LIM_NONE 0
+#define HX_LIM_MINMOD 1
+#define HX_LIM_VANLEER 2
+#define HX_LIM_VANALBADA 3
+#define HX_LIM_MLP 4
+#define HX_BC_PERIODIC 0
+#define HX_BC_TRANSMISSIVE 1
+#define HX_BC_REFLECTIVE 2
+#define HX_GRAV_NONE 0
+#define HX_GRAV_UNIFORM 1
+#define HX_GRAV_POINT 2
+#define HX_GRAV_POINT_MONOPOLE 3
+
+namespace hx {
+
+// Per-axis geometry tables (FP64, device), all indexed by cell index + ng on active axes
+// (ghost cells included), by 0 on inactive axes:
+//   cm, cp : half-width over the left / right centre distance (half increments of a slope)
+//   w      : coordinate width of the cell's image (dx; dr, dtheta, dphi)
+// Spherical extras, indexed the same way:
+//   rabs   : |r_c| of the image cell (axis 0),  sabs : |sin theta_c| of the image cell (axis 1)
+// and interior-only tables (indexed by interior index):
+//   rf[n1+1] r faces, vr[n1] (r+^3-r-^3)/3, hr[n1] (r+^2-r-^2)/2, ct[n2] cos th- - cos th+,
+//   sf[n2+1] sin of theta faces.
+struct Geo {
+    const double* cm[3];
+    const double* cp[3];
+    const double* w[3];
+    const double* rabs;
+    const double* sabs;
+    const double* rf;
+    const double* vr;
+    const double* hr;
+    const double* ct;
+    const double* sf;
+};
+
+struct SweepParams {
+    const void* U;       // U^n, SoA [nvar][n3][n2][n1], FP64 or FP32
+    void* Unew;          // U^{n+1}, same layout
+    int n[3];
+    int ng;
+    long long plane;     // n1*n2*n3
+    int bc[3][2];
+    double gamma;
+    double dt_host;
+    const double* dt_dev;  // if non-null, the step reads dt here
+    int limiter;
+    int riemann;
+    int gravity;
+    double g0[3];
+    const double* gr;    // radial acceleration per interior r index (point / monopole)
+    Geo geo;
+    int* flag;           // set to 1 when a non-physical U^n is met
+    int kz;              // z planes per block (3D)
+    const float* mlp;    // learned limiter weights (FP32 master copy)
+};
+
+}  // namespace hx

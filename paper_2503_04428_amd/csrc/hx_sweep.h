@@ -1,0 +1,608 @@
+// Fused MUSCL-Hancock step for gfx950: one kernel reads U^n once and writes U^{n+1} once.
+//
+// The scheme (paper Sect. 3.2) per cell: primitives -> limited slopes along every active axis ->
+// Hancock half step summed over the axes (unsplit) -> HLL/HLLC flux on every face ->
+// U^{n+1} = U^n + dt/dV (F_L dS_L - F_R dS_R) summed x, y, z -> + dt S (gravity, Sect. 2.2, and the
+// spherical momentum sources of Sect. 3.1.2).
+//
+// Mapping (3D): a 16x16-thread workgroup owns a 14x14 tile of (x, y) columns plus a one-cell
+// halo ring of "predictor" cells and marches along z over a chunk of planes.  Per plane:
+//   * the U^n plane k+1 is loaded (thread's own column cell into registers, the 18x18 primitive
+//     rectangle into LDS), so every plane is read from HBM once per tile;
+//   * every thread runs the Hancock predictor for its cell of plane k; x neighbours are exchanged
+//     with 16-wide wave shuffles, y neighbours through LDS, z neighbours stay in registers;
+//   * x and y fluxes of plane k and the z flux of face k-1/2 are formed; plane k-1 is finished
+//     and stored, plane k gets its x and y terms and waits for face k+1/2.
+// 1D and 2D use the same code with the inactive axes compiled out.
+#pragma once
+#include "hx_device.h"
+
+namespace hx {
+
+template <int NDIM>
+struct Tile;
+template <>
+struct Tile<1> {
+    static constexpr int BX = 64, BY = 1;
+};
+template <>
+struct Tile<2> {
+    static constexpr int BX = 16, BY = 16;
+};
+template <>
+struct Tile<3> {
+    static constexpr int BX = 16, BY = 16;
+};
+
+template <typename R>
+__device__ __forceinline__ R shfl_up1(R v, int width)
+{
+    return __shfl_up(v, 1, width);
+}
+template <typename R>
+__device__ __forceinline__ R shfl_dn1(R v, int width)
+{
+    return __shfl_down(v, 1, width);
+}
+
+// Load U^n of one (possibly ghost) cell with boundary images applied.
+template <typename R, int NV>
+__device__ __forceinline__ void fetch_cell(const SweepParams& p, const R* __restrict__ U, int ii, int jj, int kk,
+                                           bool f0, bool f1, bool f2, R* q)
+{
+    const long long off = ((long long)kk * p.n[1] + jj) * p.n[0] + ii;
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+        q[v] = U[(long long)v * p.plane + off];
+    if (f0)
+        q[1] = -q[1];
+    if (f1)
+        q[2] = -q[2];
+    if (f2)
+        q[3] = -q[3];
+}
+
+template <typename R, int NV>
+__device__ __forceinline__ bool bad_state(const R* q, const R* w)
+{
+    bool bad = !(q[0] > R(0)) || !(w[4] > R(0));
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+        bad = bad || !isfinite((double)q[v]);
+    return bad;
+}
+
+template <typename R, int NV, int NDIM, int GEOM>
+__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
+    sweep_kernel(const SweepParams p)
+{
+    using N = Num<R>;
+    constexpr int BX = Tile<NDIM>::BX;
+    constexpr int BY = Tile<NDIM>::BY;
+    constexpr int NT = BX * BY;
+    constexpr int RX = BX + 2;
+    constexpr int RY = NDIM >= 2 ? BY + 2 : 1;
+    constexpr int NSLOT = NDIM == 3 ? 2 : 1;
+    constexpr int NYB = NDIM >= 2 ? NT : 1;
+    constexpr int TX = BX - 2;
+    constexpr int TY = NDIM >= 2 ? BY - 2 : 1;
+
+    __shared__ R sW[NSLOT][NV][RY * RX];  // primitives of a plane incl. a 2-cell ring
+    __shared__ R sFy[NV][NYB];            // +y half-step state of every predictor cell
+    __shared__ R sGy[NV][NYB];            // y flux through the lower face of every cell
+
+    const R* __restrict__ U = (const R*)p.U;
+    R* __restrict__ Un = (R*)p.Unew;
+    const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2], ng = p.ng;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int x0 = blockIdx.x * TX;
+    const int y0 = NDIM >= 2 ? blockIdx.y * TY : 0;
+    // cell of this thread (clamped into the ghost range for ragged tiles)
+    const int ic = clamp_ghost(x0 + tx - 1, n0, ng);
+    const int jc = NDIM >= 2 ? clamp_ghost(y0 + ty - 1, n1, ng) : 0;
+    const bool interior = tx >= 1 && tx <= TX && (x0 + tx - 1) < n0 &&
+                          (NDIM < 2 || (ty >= 1 && ty <= TY && (y0 + ty - 1) < n1));
+    int k0 = 0, k1 = 1;
+    if (NDIM == 3) {
+        k0 = blockIdx.z * p.kz;
+        k1 = min(k0 + p.kz, n2);
+    }
+    const double dtd = p.dt_dev ? p.dt_dev[0] : p.dt_host;
+    const R dt = N::from_d(dtd);
+    Gas<R> gas;
+    gas.gamma = N::from_d(p.gamma);
+    gas.gm1 = N::from_d(p.gamma - 1.0);
+    gas.inv_gm1 = N::from_d(1.0 / (p.gamma - 1.0));
+
+    // images of this thread's x / y indices
+    bool fx, fy;
+    const int ii = bc_image(ic, n0, ng, p.bc[0][0], p.bc[0][1], fx);
+    const int jj = NDIM >= 2 ? bc_image(jc, n1, ng, p.bc[1][0], p.bc[1][1], fy) : 0;
+    if (NDIM < 2)
+        fy = false;
+    const int gx = NDIM >= 1 ? ic + ng : 0;
+    const int gy = NDIM >= 2 ? jc + ng : 0;
+
+    // per-thread geometry that does not change along z
+    const R cmx = N::from_d(p.geo.cm[0][gx]), cpx = N::from_d(p.geo.cp[0][gx]);
+    R cmy = R(0), cpy = R(0);
+    if (NDIM >= 2) {
+        cmy = N::from_d(p.geo.cm[1][gy]);
+        cpy = N::from_d(p.geo.cp[1][gy]);
+    }
+    // predictor coefficients dt / (2 width) for x and y (widths of the image cell)
+    R lamx, lamy = R(0);
+    double wx = p.geo.w[0][gx], wy = 0.0;
+    if (GEOM == HX_CART) {
+        lamx = N::from_d(dtd / (2.0 * wx));
+        if (NDIM >= 2) {
+            wy = p.geo.w[1][gy];
+            lamy = N::from_d(dtd / (2.0 * wy));
+        }
+    } else {
+        lamx = N::from_d(dtd / (2.0 * wx));
+        if (NDIM >= 2) {
+            wy = p.geo.rabs[gx] * p.geo.w[1][gy];
+            lamy = N::from_d(dtd / (2.0 * wy));
+        }
+    }
+    // gravity of this column's image (z flips handled per plane)
+    double gcol[3] = {0.0, 0.0, 0.0};
+    if (p.gravity == HX_GRAV_UNIFORM) {
+        gcol[0] = fx ? -p.g0[0] : p.g0[0];
+        gcol[1] = fy ? -p.g0[1] : p.g0[1];
+        gcol[2] = p.g0[2];
+    } else if (p.gravity != HX_GRAV_NONE) {
+        gcol[0] = fx ? -p.gr[ii] : p.gr[ii];
+    }
+
+    // ------------------------------------------------------------------ plane loader
+    // writes primitives of the (RX x RY) rectangle of plane k into slot s and returns the
+    // conserved state of this thread's own cell of that plane
+    auto load_plane = [&](int k, int s, R* qown, R* wown) {
+        bool fk = false;
+        const int kk = NDIM == 3 ? bc_image(k, n2, ng, p.bc[2][0], p.bc[2][1], fk) : 0;
+        const bool kin = NDIM < 3 || (k >= 0 && k < n2);
+        // own cell: rectangle position (tx + 1, ty + 1)
+        fetch_cell<R, NV>(p, U, ii, jj, kk, fx, fy, fk, qown);
+        to_prim<R, NV>(gas, qown, wown);
+        const int own = (NDIM >= 2 ? (ty + 1) * RX : 0) + tx + 1;
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            sW[s][v][own] = wown[v];
+        if (kin && interior && bad_state<R, NV>(qown, wown))
+            p.flag[0] = 1;
+        // ring of the rectangle
+        constexpr int NRING = NDIM >= 2 ? 2 * RX + 2 * BY : 2;
+        for (int r = tid; r < NRING; r += NT) {
+            int lx, ly;
+            if (NDIM >= 2) {
+                if (r < RX) {
+                    lx = r;
+                    ly = 0;
+                } else if (r < 2 * RX) {
+                    lx = r - RX;
+                    ly = RY - 1;
+                } else if (r < 2 * RX + BY) {
+                    lx = 0;
+                    ly = r - 2 * RX + 1;
+                } else {
+                    lx = RX - 1;
+                    ly = r - 2 * RX - BY + 1;
+                }
+            } else {
+                lx = r == 0 ? 0 : RX - 1;
+                ly = 0;
+            }
+            bool f0, f1 = false;
+            const int gi = x0 - 2 + lx;
+            const int ri = bc_image(gi, n0, ng, p.bc[0][0], p.bc[0][1], f0);
+            int rj = 0;
+            if (NDIM >= 2)
+                rj = bc_image(y0 - 2 + ly, n1, ng, p.bc[1][0], p.bc[1][1], f1);
+            R q[NV], w[NV];
+            fetch_cell<R, NV>(p, U, ri, rj, kk, f0, f1, fk, q);
+            to_prim<R, NV>(gas, q, w);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                sW[s][v][ly * RX + lx] = w[v];
+        }
+    };
+
+    // ------------------------------------------------------------------ persistent state
+    R qcur[NV], wcur[NV], qnext[NV], wnext[NV], wprev[NV];
+    R acc[NV];     // plane k-1: U^n + x and y flux terms
+    R fzlo[NV];    // z flux through the lower face of plane k-1
+    R uzp[NV];     // +z half-step state of plane k-1
+    double sg[5];  // gravity source of plane k-1 (components 1..4)
+    double sph_t[6];  // spherical partial sources of plane k-1: Trt, Trp, Tt, Xt, grg, gtg
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        acc[v] = R(0);
+        fzlo[v] = R(0);
+        uzp[v] = R(0);
+        wprev[v] = R(0);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; v++)
+        sg[v] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 6; v++)
+        sph_t[v] = 0.0;
+
+    const int own = (NDIM >= 2 ? (ty + 1) * RX : 0) + tx + 1;
+    int kbeg = k0, kend = k0;  // loop bounds over predictor planes
+    if (NDIM == 3) {
+        kbeg = k0 - 1;
+        kend = k1;
+        // own column at k0-2 (z neighbour of the first predictor plane) and plane k0-1
+        bool fk;
+        const int kk = bc_image(k0 - 2, n2, ng, p.bc[2][0], p.bc[2][1], fk);
+        R q[NV];
+        fetch_cell<R, NV>(p, U, ii, jj, kk, fx, fy, fk, q);
+        to_prim<R, NV>(gas, q, wprev);
+        load_plane(k0 - 1, (k0 - 1) & 1, qcur, wcur);
+        // a valid state for the (unused) z flux below the first predictor plane
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            uzp[v] = qcur[v];
+    } else {
+        load_plane(0, 0, qcur, wcur);
+    }
+    __syncthreads();
+
+    for (int k = kbeg; k <= kend; ++k) {
+        const int slot = NDIM == 3 ? (k & 1) : 0;
+        if (NDIM == 3)
+            load_plane(k + 1, (k + 1) & 1, qnext, wnext);
+
+        // -------------------------------------------------------------- predictor, plane k
+        bool fzk = false;
+        int kk = 0, gz = 0;
+        R cmz = R(0), cpz = R(0), lamz = R(0);
+        double g[3] = {gcol[0], gcol[1], gcol[2]};
+        if (NDIM == 3) {
+            const int kc = clamp_ghost(k, n2, ng);
+            kk = bc_image(kc, n2, ng, p.bc[2][0], p.bc[2][1], fzk);
+            gz = kc + ng;
+            cmz = N::from_d(p.geo.cm[2][gz]);
+            cpz = N::from_d(p.geo.cp[2][gz]);
+            double wz = GEOM == HX_CART ? p.geo.w[2][gz] : p.geo.rabs[gx] * p.geo.sabs[gy] * p.geo.w[2][gz];
+            lamz = N::from_d(dtd / (2.0 * wz));
+            if (fzk && p.gravity == HX_GRAV_UNIFORM)
+                g[2] = -g[2];
+        }
+        R dlt[3][NV];  // half increments of the limited slopes
+        R du[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            du[v] = R(0);
+            dlt[0][v] = dlt[1][v] = dlt[2][v] = R(0);
+        }
+        {
+            // x
+            R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                R a = cmx * (wcur[v] - sW[slot][v][own - 1]);
+                R b = cpx * (sW[slot][v][own + 1] - wcur[v]);
+                R d = limit<R>(p.limiter, a, b);
+                dlt[0][v] = d;
+                wm[v] = wcur[v] - d;
+                wp[v] = wcur[v] + d;
+            }
+            to_cons<R, NV>(gas, wm, um);
+            to_cons<R, NV>(gas, wp, up);
+            phys_flux<R, NV, 0>(wm, um, fm);
+            phys_flux<R, NV, 0>(wp, up, fp);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                du[v] += lamx * (fm[v] - fp[v]);
+        }
+        if (NDIM >= 2) {
+            R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                R a = cmy * (wcur[v] - sW[slot][v][own - RX]);
+                R b = cpy * (sW[slot][v][own + RX] - wcur[v]);
+                R d = limit<R>(p.limiter, a, b);
+                dlt[1][v] = d;
+                wm[v] = wcur[v] - d;
+                wp[v] = wcur[v] + d;
+            }
+            to_cons<R, NV>(gas, wm, um);
+            to_cons<R, NV>(gas, wp, up);
+            phys_flux<R, NV, 1>(wm, um, fm);
+            phys_flux<R, NV, 1>(wp, up, fp);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                du[v] += lamy * (fm[v] - fp[v]);
+        }
+        if (NDIM == 3) {
+            R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                R a = cmz * (wcur[v] - wprev[v]);
+                R b = cpz * (wnext[v] - wcur[v]);
+                R d = limit<R>(p.limiter, a, b);
+                dlt[2][v] = d;
+                wm[v] = wcur[v] - d;
+                wp[v] = wcur[v] + d;
+            }
+            to_cons<R, NV>(gas, wm, um);
+            to_cons<R, NV>(gas, wp, up);
+            phys_flux<R, NV, 2>(wm, um, fm);
+            phys_flux<R, NV, 2>(wp, up, fp);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                du[v] += lamz * (fm[v] - fp[v]);
+        }
+        if (p.gravity != HX_GRAV_NONE) {
+            // (dt/2) S(U^n) with S = (0, rho g, m.g, 0)
+            R hs = R(0.5) * dt;
+            R S[5];
+            S[0] = R(0);
+            S[1] = qcur[0] * N::from_d(g[0]);
+            S[2] = qcur[0] * N::from_d(g[1]);
+            S[3] = qcur[0] * N::from_d(g[2]);
+            S[4] = qcur[1] * N::from_d(g[0]) + qcur[2] * N::from_d(g[1]) + qcur[3] * N::from_d(g[2]);
+#pragma unroll
+            for (int v = 0; v < 5; v++)
+                du[v] += hs * S[v];
+#pragma unroll
+            for (int v = 5; v < NV; v++)
+                du[v] += hs * R(0);
+        }
+        // positivity of all half-step face states; otherwise first order for this cell
+        bool bad = false;
+#pragma unroll
+        for (int d = 0; d < NDIM; d++) {
+#pragma unroll
+            for (int side = 0; side < 2; side++) {
+                R ws[NV], qs[NV], wq[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    ws[v] = side ? wcur[v] + dlt[d][v] : wcur[v] - dlt[d][v];
+                to_cons<R, NV>(gas, ws, qs);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    qs[v] += du[v];
+                to_prim<R, NV>(gas, qs, wq);
+                bad = bad || !(qs[0] > R(0)) || !(wq[4] > R(0));
+            }
+        }
+        if (bad) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                du[v] = R(0);
+                dlt[0][v] = dlt[1][v] = dlt[2][v] = R(0);
+            }
+        }
+        // final half-step face states: cons(W -/+ delta) + du (or cons(W) in the fallback)
+        auto face_state = [&](int d, int side, R* out) {
+            R ws[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                ws[v] = side ? wcur[v] + dlt[d][v] : wcur[v] - dlt[d][v];
+            to_cons<R, NV>(gas, ws, out);
+            if (!bad) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    out[v] += du[v];
+            }
+        };
+        R uh[NV];  // cell half-step state for the sources
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            uh[v] = bad ? qcur[v] : qcur[v] + du[v];
+
+        R qmx[NV], qpx[NV];
+        face_state(0, 0, qmx);
+        face_state(0, 1, qpx);
+        R qmy[NV];
+        if (NDIM >= 2) {
+            R qpy[NV];
+            face_state(1, 0, qmy);
+            face_state(1, 1, qpy);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                sFy[v][tid] = qpy[v];
+        }
+        R qmz[NV], qpz[NV];
+        if (NDIM == 3) {
+            face_state(2, 0, qmz);
+            face_state(2, 1, qpz);
+        }
+        __syncthreads();
+
+        // -------------------------------------------------------------- fluxes
+        const bool plane_live = NDIM < 3 || (k >= k0 && k < k1);
+        R Fx[NV], Fy[NV], Fz[NV];
+        {
+            R L[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                L[v] = shfl_up1(qpx[v], BX);
+            if (tx == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    L[v] = qmx[v];
+            }
+            riemann<R, NV, 0>(p.riemann, gas, L, qmx, Fx);
+        }
+        if (NDIM >= 2) {
+            R L[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                L[v] = ty > 0 ? sFy[v][tid - BX] : qmy[v];
+            riemann<R, NV, 1>(p.riemann, gas, L, qmy, Fy);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                sGy[v][tid] = Fy[v];
+        }
+        if (NDIM == 3) {
+            riemann<R, NV, 2>(p.riemann, gas, uzp, qmz, Fz);
+        }
+        __syncthreads();
+
+        // -------------------------------------------------------------- update
+        R Fxr[NV], Fyu[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            Fxr[v] = shfl_dn1(Fx[v], BX);
+        if (NDIM >= 2) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                Fyu[v] = ty < BY - 1 ? sGy[v][tid + BX] : Fy[v];
+        }
+
+        if (interior) {
+            // finish plane k-1 with its z terms and sources, then store it
+            if (NDIM == 3 && k - 1 >= k0) {
+                const int kp = k - 1;
+                if (GEOM == HX_CART) {
+                    const R mu = N::from_d(dtd / p.geo.w[2][kp + ng]);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] += mu * (fzlo[v] - Fz[v]);
+                } else {
+                    const double dph = p.geo.w[2][kp + ng];
+                    const double dV = p.geo.vr[ii] * p.geo.ct[jj] * dph;
+                    const R kv = N::from_d(dtd / dV);
+                    const R dS = N::from_d(p.geo.hr[ii] * p.geo.w[1][jj + ng]);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] += kv * (fzlo[v] * dS - Fz[v] * dS);
+                }
+                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
+                    double S[5] = {0.0, sg[1], sg[2], sg[3], sg[4]};
+                    if (GEOM == HX_SPH) {
+                        const double Xp = 0.5 * ((double)fzlo[3] + (double)Fz[3]);
+                        S[1] = S[1] + 0.5 * (sph_t[3] + Xp) * sph_t[4];
+                        S[2] = S[2] + (sph_t[0] + Xp * sph_t[5]);
+                        S[3] = S[3] + (sph_t[1] + sph_t[2]);
+                    }
+#pragma unroll
+                    for (int v = 1; v < 5; v++)
+                        acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
+                }
+                const long long off = ((long long)kp * n1 + jj) * n0 + ii;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    Un[(long long)v * p.plane + off] = acc[v];
+            }
+            if (plane_live) {
+                // x and y terms of plane k
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    acc[v] = qcur[v];
+                double dV = 0.0, dSrm = 0.0, dSrp = 0.0, dStm = 0.0, dStp = 0.0, dph = 1.0;
+                if (GEOM == HX_CART) {
+                    const R mu = N::from_d(dtd / wx);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] += mu * (Fx[v] - Fxr[v]);
+                    if (NDIM >= 2) {
+                        const R muy = N::from_d(dtd / wy);
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            acc[v] += muy * (Fy[v] - Fyu[v]);
+                    }
+                } else {
+                    const int kin = NDIM == 3 ? k : 0;
+                    dph = p.geo.w[2][NDIM == 3 ? kin + ng : 0];
+                    const double ctj = p.geo.ct[jj];
+                    dV = p.geo.vr[ii] * ctj * dph;
+                    const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
+                    dSrm = rm * rm * ctj * dph;
+                    dSrp = rp * rp * ctj * dph;
+                    const double kvd = dtd / dV;
+                    const R kv = N::from_d(kvd);
+                    const R sm = N::from_d(dSrm), sp = N::from_d(dSrp);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] += kv * (Fx[v] * sm - Fxr[v] * sp);
+                    if (NDIM >= 2) {
+                        dStm = p.geo.hr[ii] * p.geo.sf[jj] * dph;
+                        dStp = p.geo.hr[ii] * p.geo.sf[jj + 1] * dph;
+                        const R tm = N::from_d(dStm), tp = N::from_d(dStp);
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            acc[v] += kv * (Fy[v] * tm - Fyu[v] * tp);
+                    }
+                }
+                // sources of plane k (finished now in 1D/2D, after the z terms in 3D)
+                double S[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                if (p.gravity != HX_GRAV_NONE) {
+                    S[1] = (double)uh[0] * g[0];
+                    S[2] = (double)uh[0] * g[1];
+                    S[3] = (double)uh[0] * g[2];
+                    S[4] = (double)uh[1] * g[0] + (double)uh[2] * g[1] + (double)uh[3] * g[2];
+                }
+                if (GEOM == HX_SPH) {
+                    const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
+                    const double cr = (rp - rm) / ((rp + rm) * dV);
+                    const double grg = (dSrp - dSrm) / dV;
+                    double pu = 0.0;
+                    if (NDIM < 3) {
+                        R wu[NV];
+                        to_prim<R, NV>(gas, uh, wu);
+                        pu = (double)wu[4];
+                    }
+                    double Xt, Tt = 0.0, gtg = 0.0;
+                    if (NDIM >= 2) {
+                        const double smm = p.geo.sf[jj], spp = p.geo.sf[jj + 1];
+                        const double ctc = (spp - smm) / ((spp + smm) * dV);
+                        gtg = (dStp - dStm) / dV;
+                        Xt = 0.5 * ((double)Fy[2] + (double)Fyu[2]);
+                        Tt = -ctc * ((double)Fyu[3] * dStp + (double)Fy[3] * dStm);
+                    } else {
+                        Xt = (double)uh[2] * ((double)uh[2] / (double)uh[0]) + pu;
+                    }
+                    const double Trt = -cr * ((double)Fxr[2] * dSrp + (double)Fx[2] * dSrm);
+                    const double Trp = -cr * ((double)Fxr[3] * dSrp + (double)Fx[3] * dSrm);
+                    if (NDIM == 3) {
+                        sph_t[0] = Trt;
+                        sph_t[1] = Trp;
+                        sph_t[2] = Tt;
+                        sph_t[3] = Xt;
+                        sph_t[4] = grg;
+                        sph_t[5] = gtg;
+                    } else {
+                        const double Xp = (double)uh[3] * ((double)uh[3] / (double)uh[0]) + pu;
+                        S[1] = S[1] + 0.5 * (Xt + Xp) * grg;
+                        S[2] = S[2] + (Trt + Xp * gtg);
+                        S[3] = S[3] + (Trp + Tt);
+                    }
+                }
+                if (NDIM == 3) {
+#pragma unroll
+                    for (int v = 1; v < 5; v++)
+                        sg[v] = S[v];
+                } else {
+                    if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
+#pragma unroll
+                        for (int v = 1; v < 5; v++)
+                            acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
+                    }
+                    const long long off = ((long long)jj * n0) + ii;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        Un[(long long)v * p.plane + off] = acc[v];
+                }
+            }
+        }
+        if (NDIM == 3) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                fzlo[v] = Fz[v];
+                uzp[v] = qpz[v];
+                wprev[v] = wcur[v];
+                wcur[v] = wnext[v];
+                qcur[v] = qnext[v];
+            }
+        }
+    }
+}
+
+}  // namespace hx

@@ -1,0 +1,249 @@
+"""Python binding of libhydro.so (the gfx950 MUSCL-Hancock step behind the C ABI of
+include/hydro.h).  Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the HIP stream.
+
+The binding refuses to work without the built library and a HIP device: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+
+OK, EINVAL, EHIP, ENONPHYS, ESTATE, ENOSPACE = 0, -1, -2, -3, -4, -5
+MLP_NPARAM = 1249
+
+GEOM = {"cart": 0, "sph": 1}
+RIEMANN = {"hll": 0, "hllc": 1}
+LIMITER = {"none": 0, "minmod": 1, "vanleer": 2, "vanalbada": 3, "mlp": 4}
+PRECISION = {"fp64": 0, "fp32": 1}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+GRAVITY = {"none": 0, "uniform": 1, "point": 2, "point_monopole": 3}
+
+_DP = C.POINTER(C.c_double)
+
+
+class HxConfig(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int), ("geom", C.c_int), ("n", C.c_int * 3), ("nghost", C.c_int),
+        ("faces", _DP * 3), ("nscalar", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double),
+        ("riemann", C.c_int), ("limiter", C.c_int), ("precision", C.c_int),
+        ("bc", (C.c_int * 2) * 3), ("gravity", C.c_int), ("g0", C.c_double * 3),
+        ("G", C.c_double), ("Mc", C.c_double),
+    ]
+
+
+class HydroError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hydro status {status}: {msg}")
+        self.status = status
+
+
+class NonPhysicalState(HydroError):
+    pass
+
+
+_lib = None
+
+# names of the exported entry points, as declared in include/hydro.h
+EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
+           "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
+           "hx_set_zchunk", "hx_enclosed_mass", "hx_last_error", "hx_destroy"]
+
+
+def load_library():
+    """Load libhydro.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    cfgp = C.POINTER(HxConfig)
+    vp = C.c_void_p
+    L.hx_workspace_bytes.argtypes = [cfgp]
+    L.hx_workspace_bytes.restype = C.c_size_t
+    L.hx_create.argtypes = [cfgp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.hx_set_state.argtypes = [vp, vp]
+    L.hx_get_state.argtypes = [vp, vp]
+    L.hx_compute_dt.argtypes = [vp, _DP]
+    L.hx_compute_dt_device.argtypes = [vp, vp]
+    L.hx_step.argtypes = [vp, C.c_double]
+    L.hx_step_device.argtypes = [vp, vp]
+    L.hx_totals.argtypes = [vp, _DP]
+    L.hx_check.argtypes = [vp]
+    L.hx_set_mlp.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+    L.hx_set_zchunk.argtypes = [vp, C.c_int]
+    L.hx_enclosed_mass.argtypes = [vp, _DP]
+    L.hx_last_error.argtypes = []
+    L.hx_last_error.restype = C.c_char_p
+    L.hx_destroy.argtypes = [vp]
+    L.hx_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("hx_workspace_bytes", "hx_last_error", "hx_destroy"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _get(p, k):
+    return p[k] if isinstance(p, dict) else getattr(p, k)
+
+
+def make_config(prob, precision: str | None = None):
+    """hx_config for a problem description (see problems.Problem); returns (config, keepalive)."""
+    c = HxConfig()
+    ndim = int(_get(prob, "ndim"))
+    c.ndim = ndim
+    c.geom = GEOM[_get(prob, "geom")]
+    faces = [np.ascontiguousarray(f, dtype=np.float64) for f in _get(prob, "faces")]
+    for d in range(3):
+        c.n[d] = int(_get(prob, "n")[d])
+        c.faces[d] = faces[d].ctypes.data_as(_DP)
+        c.bc[d][0] = BC[_get(prob, "bc")[d][0]]
+        c.bc[d][1] = BC[_get(prob, "bc")[d][1]]
+        c.g0[d] = float(_get(prob, "g0")[d])
+    c.nghost = int(_get(prob, "ng"))
+    c.nscalar = int(_get(prob, "nscalar"))
+    c.gamma = float(_get(prob, "gamma"))
+    c.cfl = float(_get(prob, "cfl"))
+    c.riemann = RIEMANN[_get(prob, "riemann")]
+    c.limiter = LIMITER[_get(prob, "limiter")]
+    c.precision = PRECISION[precision or _get(prob, "precision")]
+    c.gravity = GRAVITY[_get(prob, "gravity")]
+    c.G = float(_get(prob, "G"))
+    c.Mc = float(_get(prob, "Mc"))
+    return c, faces
+
+
+def workspace_bytes(prob, precision: str | None = None) -> int:
+    L = load_library()
+    c, keep = make_config(prob, precision)
+    n = L.hx_workspace_bytes(C.byref(c))
+    if n == 0:
+        raise HydroError(EINVAL, L.hx_last_error().decode())
+    return int(n)
+
+
+class Solver:
+    """One solver context on a torch CUDA (HIP) device and stream."""
+
+    def __init__(self, prob, precision: str | None = None, device="cuda", stream=None, zchunk: int | None = None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("hydro.Solver needs a HIP device; there is no CPU path")
+        self.torch = torch
+        self.L = load_library()
+        self.prob = prob
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.cfg, self._faces = make_config(prob, precision)
+        self.nvar = 5 + int(_get(prob, "nscalar"))
+        n = [int(v) for v in _get(prob, "n")]
+        self.shape = (self.nvar, n[2], n[1], n[0])
+        nbytes = self.L.hx_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise HydroError(EINVAL, self.L.hx_last_error().decode())
+        # over-allocate so the workspace can be aligned to 256 bytes
+        self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws_raw.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.workspace_bytes = nbytes
+        ctx = C.c_void_p()
+        self._call(self.L.hx_create(C.byref(self.cfg), C.c_void_p(self._ws_ptr), C.c_size_t(nbytes),
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+        self._dt_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+        if zchunk is not None:
+            self.set_zchunk(zchunk)
+
+    def _call(self, st: int):
+        if st != OK:
+            msg = self.L.hx_last_error().decode()
+            if st == ENONPHYS:
+                raise NonPhysicalState(st, msg)
+            raise HydroError(st, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.hx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- state
+    def set_state(self, U):
+        torch = self.torch
+        if isinstance(U, np.ndarray):
+            t = torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape)).to(self.device)
+        else:
+            t = U.to(device=self.device, dtype=torch.float64).contiguous().reshape(self.shape)
+        self._state_in = t  # keep alive until the async copy has run
+        with torch.cuda.stream(self.stream):
+            self._call(self.L.hx_set_state(self.ctx, C.c_void_p(t.data_ptr())))
+
+    def get_state(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._call(self.L.hx_get_state(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def state_numpy(self) -> np.ndarray:
+        t = self.get_state()
+        self.stream.synchronize()
+        return t.cpu().numpy()
+
+    # ----------------------------------------------------------------- stepping
+    def compute_dt(self) -> float:
+        dt = C.c_double(0.0)
+        self._call(self.L.hx_compute_dt(self.ctx, C.byref(dt)))
+        return dt.value
+
+    def compute_dt_device(self, d_dt=None):
+        d_dt = self._dt_dev if d_dt is None else d_dt
+        self._call(self.L.hx_compute_dt_device(self.ctx, C.c_void_p(d_dt.data_ptr())))
+        return d_dt
+
+    def step(self, dt: float):
+        self._call(self.L.hx_step(self.ctx, C.c_double(float(dt))))
+
+    def step_device(self, d_dt=None):
+        d_dt = self._dt_dev if d_dt is None else d_dt
+        self._call(self.L.hx_step_device(self.ctx, C.c_void_p(d_dt.data_ptr())))
+
+    def advance(self, nsteps: int):
+        """nsteps CFL steps without host synchronisation (dt computed on the device)."""
+        for _ in range(nsteps):
+            self.compute_dt_device()
+            self.step_device()
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(self.nvar)
+        self._call(self.L.hx_totals(self.ctx, out.ctypes.data_as(_DP)))
+        return out
+
+    def check(self):
+        self._call(self.L.hx_check(self.ctx))
+
+    def set_mlp(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._call(self.L.hx_set_mlp(self.ctx, w.ctypes.data_as(C.POINTER(C.c_float)), C.c_size_t(w.size)))
+
+    def set_zchunk(self, kz: int):
+        self._call(self.L.hx_set_zchunk(self.ctx, int(kz)))
+
+    def enclosed_mass(self) -> np.ndarray:
+        out = np.zeros(int(_get(self.prob, "n")[0]))
+        self._call(self.L.hx_enclosed_mass(self.ctx, out.ctypes.data_as(_DP)))
+        return out

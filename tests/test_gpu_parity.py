@@ -1,0 +1,211 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle on the same seeded
+inputs.  FP64 bar: per cell |dU| <= 1e-12 |U_oracle| + 1e-14 max|U_oracle,field|, after up to 100
+steps, on small grids spanning several workgroup tiles with ragged tails, every boundary type,
+limiter, Riemann solver, gravity mode, geometry and scalar count; and at full size on sampled
+cells of the first step."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2503_04428_amd import problems as P
+
+from parity import announce, assert_parity, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2503_04428_amd import hydro
+    hydro.load_library()
+    return hydro
+
+
+def run_pair(H, prob, nsteps, zchunk=None, check_dt=True):
+    o = O.Oracle(prob)
+    s = H.Solver(prob, zchunk=zchunk)
+    U = prob.U0.copy()
+    s.set_state(U)
+    for n in range(nsteps):
+        dt, st = o.compute_dt(U)
+        assert st == 0
+        if check_dt and n in (0, nsteps - 1):
+            dtg = s.compute_dt()
+            assert dtg == pytest.approx(dt, rel=1e-14, abs=0), (dtg, dt)
+        U, st = o.step(U, dt)
+        assert st == 0
+        s.step(dt)
+    Ug = s.state_numpy()
+    s.close()
+    return Ug, U
+
+
+CASES = {
+    # 1D
+    "sod1024_vl_hllc_100": (lambda: P.sod(1024), 100, None),
+    "sod300_minmod_hll": (lambda: P.sod(300, limiter="minmod", riemann="hll"), 40, None),
+    "sod300_vanalbada_hllc": (lambda: P.sod(300, limiter="vanalbada"), 40, None),
+    "sod300_none_hllc": (lambda: P.sod(300, limiter="none"), 40, None),
+    "rand1d_periodic_s2": (lambda: P.random_periodic(n=(131,), ndim=1, nscalar=2, seed=21), 40, None),
+    # 2D
+    "rand2d_periodic_s1": (lambda: P.random_periodic(n=(37, 29), ndim=2, nscalar=1, seed=22), 40, None),
+    "rand2d_mixed_hll_s3": (lambda: P.random_periodic(
+        n=(30, 17), ndim=2, nscalar=3, seed=23, riemann="hll", limiter="minmod",
+        bc=[["transmissive", "reflective"], ["reflective", "transmissive"], ["periodic"] * 2]), 40, None),
+    "liska40": (lambda: P.liska(40), 40, None),
+    "rt2d_24x48_gravity": (lambda: P.rt2d(24, 48), 40, None),
+    # 3D
+    "rand3d_periodic_s2_kz8": (lambda: P.random_periodic(n=(31, 23, 19), ndim=3, nscalar=2, seed=24), 30, 8),
+    "rand3d_mixed_s3_kz5": (lambda: P.random_periodic(
+        n=(17, 20, 13), ndim=3, nscalar=3, seed=25, limiter="vanalbada",
+        bc=[["transmissive"] * 2, ["reflective"] * 2, ["periodic"] * 2]), 30, 5),
+    "rand3d_hll_s0_kz32": (lambda: P.random_periodic(n=(15, 16, 33), ndim=3, nscalar=0, seed=26,
+                                                       riemann="hll"), 30, 32),
+    "sedov32_100": (lambda: P.sedov3d(n=32), 100, 8),
+    "rt3d_16x16x48": (lambda: P.rt3d(16, 16, 48, precision="fp64"), 50, 12),
+    "free_fall3d": (lambda: P.free_fall(), 20, 2),
+    # spherical
+    "wedge3d_monopole_s4": (lambda: P.random_wedge(
+        nr=17, nth=15, nph=13, nscalar=4, gravity="point_monopole",
+        bc=[["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2]), 30, 4),
+    "wedge3d_point_refl": (lambda: P.random_wedge(
+        nr=16, nth=9, nph=20, nscalar=1, gravity="point",
+        bc=[["reflective"] * 2, ["reflective"] * 2, ["reflective"] * 2]), 30, 7),
+    "wedge2d_point": (lambda: P.random_wedge(nr=20, nth=18, ndim=2, nscalar=1, gravity="point",
+                                             bc=[["reflective", "transmissive"], ["reflective"] * 2,
+                                                 ["periodic"] * 2]), 30, None),
+    "sedov_sph1d_100": (lambda: P.sedov_sph1d(100), 100, None),
+    "static_wedge": (lambda: P.static_wedge(), 30, 3),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_parity_small(H, name):
+    make, nsteps, kz = CASES[name]
+    prob = make()
+    announce(f"fp64 parity {name} n={prob.n} nvar={prob.nvar} steps={nsteps} kz={kz}")
+    Ug, Uo = run_pair(H, prob, nsteps, zchunk=kz)
+    assert_parity(Ug, Uo, what=name)
+    print(f"{name}: max relative difference {max_rel(Ug, Uo):.3e}")
+
+
+def test_fp64_parity_full_size_sedov_sampled(H):
+    """Sedov 256^3 in the benchmark's launch configuration: the first step on sampled boxes (the
+    blast centre, random interior boxes, tile and chunk seams, the domain corners)."""
+    prob = P.sedov3d(n=256)
+    announce("fp64 full-size sedov 256^3 first step")
+    o = O.Oracle(prob)
+    U0 = prob.U0
+    dt, st = o.compute_dt(U0)
+    s = H.Solver(prob)
+    s.set_state(U0)
+    dtg = s.compute_dt()
+    assert dtg == pytest.approx(dt, rel=1e-14, abs=0)
+    s.step(dt)
+    Ug = s.state_numpy()
+    s.close()
+    rng = np.random.default_rng(0)
+    boxes = [((124, 124, 124), (132, 132, 132)), ((0, 0, 0), (3, 3, 3)), ((253, 253, 253), (256, 256, 256)),
+             ((12, 12, 30), (17, 17, 34)), ((138, 26, 62), (142, 30, 66))]
+    for _ in range(6):
+        lo = rng.integers(0, 252, size=3)
+        boxes.append((tuple(int(v) for v in lo), tuple(int(v) + 4 for v in lo)))
+    for lo, hi in boxes:
+        ob, st = o.step_box(U0, dt, lo, hi)
+        gb = Ug[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        assert_parity(gb, ob, what=f"sedov256 box {lo}-{hi}")
+
+
+def test_dt_and_totals_match_oracle(H):
+    prob = P.random_wedge(nr=21, nth=11, nph=9, nscalar=2, gravity="point_monopole",
+                          bc=[["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2])
+    announce("dt/totals/enclosed-mass parity")
+    o = O.Oracle(prob)
+    s = H.Solver(prob)
+    s.set_state(prob.U0)
+    dt, _ = o.compute_dt(prob.U0)
+    assert s.compute_dt() == dt
+    tg = s.totals()
+    to = o.totals(prob.U0)
+    assert np.allclose(tg, to, rtol=1e-13, atol=0)
+    s.step(dt)
+    s.check()
+    me = s.enclosed_mass()
+    mo = o.enclosed_mass(prob.U0)
+    assert np.allclose(me, mo, rtol=1e-13)
+    s.close()
+
+
+def test_nonphysical_state_reported(H):
+    prob = P.random_periodic(n=(20, 18, 9), ndim=3, nscalar=1)
+    announce("non-physical state report")
+    U = prob.U0.copy()
+    U[0, 3, 4, 5] = -1.0
+    s = H.Solver(prob)
+    s.set_state(U)
+    with pytest.raises(H.NonPhysicalState):
+        s.compute_dt()
+    # a fresh valid state clears the report
+    s.set_state(prob.U0)
+    assert s.compute_dt() > 0
+    U = prob.U0.copy()
+    U[4, 1, 2, 3] = np.nan
+    s.set_state(U)
+    s.step(1e-4)
+    with pytest.raises(H.NonPhysicalState):
+        s.check()
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_resume_bitwise(H, precision):
+    prob = P.random_periodic(n=(23, 19, 17), ndim=3, nscalar=2, seed=3)
+    announce(f"checkpoint/resume {precision}")
+    a = H.Solver(prob, precision=precision)
+    a.set_state(prob.U0)
+    a.advance(10)
+    ref = a.state_numpy()
+    b = H.Solver(prob, precision=precision)
+    b.set_state(prob.U0)
+    b.advance(5)
+    mid = b.get_state()
+    c = H.Solver(prob, precision=precision)
+    c.set_state(mid)
+    c.advance(5)
+    assert np.array_equal(c.state_numpy(), ref)
+    for x in (a, b, c):
+        x.close()
+
+
+def test_device_dt_loop_equals_host_dt_loop(H):
+    prob = P.sedov3d(n=32)
+    announce("device-dt loop")
+    a = H.Solver(prob)
+    a.set_state(prob.U0)
+    for _ in range(12):
+        a.step(a.compute_dt())
+    b = H.Solver(prob)
+    b.set_state(prob.U0)
+    b.advance(12)
+    assert np.array_equal(a.state_numpy(), b.state_numpy())
+
+
+def test_zchunk_does_not_change_results(H):
+    prob = P.random_periodic(n=(18, 17, 29), ndim=3, nscalar=1, seed=9,
+                             bc=[["reflective"] * 2, ["transmissive"] * 2, ["reflective"] * 2])
+    announce("z-chunk invariance")
+    outs = []
+    for kz in (1, 3, 29, 64):
+        s = H.Solver(prob, zchunk=kz)
+        s.set_state(prob.U0)
+        for _ in range(5):
+            s.step(2e-3)
+        outs.append(s.state_numpy())
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
