@@ -1,0 +1,193 @@
+"""Benchmark: zone-cycles/s of the MUSCL-Hancock step on one MI355X.
+
+Workload: 3D Cartesian Sedov blast, 256^3 cells, 7 fields (5 conserved + 2 passive scalars),
+HLLC, van Leer, CFL 0.5 -- the plain FP64 path (the headline value) and the FP32 form, each a
+sequence of steps; one step = the CFL dt reduction + the fused sweep, with the time step kept on
+the device (no host synchronisation inside the timed loop).  Inputs are synthetic and resident in
+HBM before the timed region starts.
+
+Prints one JSON line (see the contract in the repository's documentation).  The roofline block
+refers to the dominant kernel, the fused sweep: algorithmic bytes per launch = 2 * nvar * b * cells
+(U^n read once, U^{n+1} written once), divided by the sweep's average duration measured with HIP
+events on the stream it runs on.  The cpu_baseline block times the FP64 oracle (single-threaded,
+as it stands) on a bounded slab of the same first step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(hydro, torch, prob, form, steps, warmup, zchunk):
+    s = hydro.Solver(prob, precision=form, zchunk=zchunk)
+    s.set_state(prob.U0)
+    stream = s.stream
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        t_start.record(stream)
+        for a, b in evs:
+            s.compute_dt_device()
+            a.record(stream)
+            s.step_device()
+            b.record(stream)
+        t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    gpu_ms = t_start.elapsed_time(t_end)
+    sweep_ms = [a.elapsed_time(b) for a, b in evs]
+    s.check()
+    state = s.get_state()
+    torch.cuda.synchronize()
+    out = {
+        "form": form,
+        "wall_s": wall,
+        "gpu_ms": gpu_ms,
+        "ms_per_step": wall * 1e3 / steps,
+        "sweep_ms_avg": sum(sweep_ms) / len(sweep_ms),
+        "sweep_ms_min": min(sweep_ms),
+        "state": state,
+    }
+    s.close()
+    return out
+
+
+def cpu_baseline(prob, nz_slab):
+    """FP64 oracle (single-threaded C, as it stands) on an nx*ny*nz_slab slab of the first step."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    o = O.Oracle(prob)
+    dt, _ = o.compute_dt(prob.U0)
+    n = prob.n
+    z0 = n[2] // 2 - nz_slab // 2
+    lo, hi = (0, 0, z0), (n[0], n[1], z0 + nz_slab)
+    t0 = time.perf_counter()
+    _, st = o.step_box(prob.U0, dt, lo, hi)
+    el = time.perf_counter() - t0
+    cells = n[0] * n[1] * nz_slab
+    return {"value": cells / el, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"one step of the {n[0]}x{n[1]}x{nz_slab} central slab of the {n[0]}x{n[1]}x{n[2]} "
+                      f"Sedov state ({cells} cells, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis of the Sedov cube")
+    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--zchunk", type=int, default=None)
+    ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU domain decomposition is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
+        print("bench.py runs as a single process on one GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2503_04428_amd import hydro, problems
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    hydro.load_library()
+    prob = problems.sedov3d(n=args.n)
+    cells = prob.ncells
+    nvar = prob.nvar
+    log(f"workload: sedov 3D {args.n}^3, nvar {nvar}, steps {args.steps}, warmup {args.warmup}")
+
+    results = {}
+    for form in [f.strip() for f in args.forms.split(",") if f.strip()]:
+        r = run_form(hydro, torch, prob, form, args.steps, args.warmup, args.zchunk)
+        log(f"{form}: {r['ms_per_step']:.3f} ms/step, sweep {r['sweep_ms_avg']:.3f} ms "
+            f"(min {r['sweep_ms_min']:.3f}), {cells * args.steps / r['wall_s']:.3e} zone-cycles/s")
+        results[form] = r
+
+    # accuracy of the FP32 form against the FP64 path (same initial state, same number of steps)
+    l1 = None
+    if "fp64" in results and "fp32" in results:
+        a = results["fp64"]["state"]
+        b = results["fp32"]["state"]
+        diff = (b - a).abs().reshape(nvar, -1).mean(dim=1)
+        ref = a.abs().reshape(nvar, -1).mean(dim=1)
+        l1 = (diff / ref).cpu().numpy().tolist()
+    for r in results.values():
+        del r["state"]
+
+    head = results.get("fp64") or next(iter(results.values()))
+    rb = 8 if head["form"] == "fp64" else 4
+    value = cells * args.steps / head["wall_s"]
+    alg_bytes = 2 * nvar * rb * cells
+    achieved = alg_bytes / (head["sweep_ms_avg"] * 1e-3) / 1e9
+    forms = {}
+    for f, r in results.items():
+        b = 8 if f == "fp64" else 4
+        forms[f] = {
+            "zone_cycles_per_s": cells * args.steps / r["wall_s"],
+            "ms_per_step": r["ms_per_step"],
+            "sweep_ms": r["sweep_ms_avg"],
+            "sweep_hbm_gbs_algorithmic": 2 * nvar * b * cells / (r["sweep_ms_avg"] * 1e-3) / 1e9,
+            "speedup_vs_fp64": (results["fp64"]["wall_s"] / r["wall_s"]) if "fp64" in results else None,
+        }
+    if l1 is not None:
+        forms["fp32"]["l1_rel_vs_fp64_per_field"] = l1
+
+    cpu = None
+    if args.cpu_slab > 0:
+        log("timing the CPU oracle ...")
+        cpu = cpu_baseline(prob, args.cpu_slab)
+        log(f"oracle: {cpu['value']:.3e} zone-cycles/s on 1 core")
+
+    line = {
+        "metric": "zone-cycles/s on 1 GPU (FP64 vs FP32 vs learned limiter) at stated L1 error",
+        "value": value,
+        "unit": "zone-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head["form"] == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sedov3d-{args.n}^3 (5 conserved + 2 passive scalars, HLLC, van Leer, CFL 0.5)",
+                   "cells": cells, "nvar": nvar, "form": head["form"], "dt": "CFL, on device every step"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "hx::sweep_kernel (fused MUSCL-Hancock sweep)",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,8 +186,9 @@ static void gravity_at(const Ctx *x, int i, int j, int k, double g[3])
 
 /* ------------------------------------------------------------------ EoS and fluxes */
 
-/* primitives (rho, u1, u2, u3, P, f...) from conserved (Sect. 2.1, eq. eos_gas) */
-static void prim(const Ctx *x, const double *q, double *w)
+/* primitives (rho, u1, u2, u3, P, f...) from conserved (Sect. 2.1, eq. eos_gas); the reciprocal
+ * density is returned for the sound speed and the HLLC star energy */
+static double prim_inv(const Ctx *x, const double *q, double *w)
 {
     double rho = q[0];
     double inv = 1.0 / rho;
@@ -200,7 +201,10 @@ static void prim(const Ctx *x, const double *q, double *w)
     w[4] = x->gm1 * (q[4] - ke);
     for (int v = 5; v < x->nvar; v++)
         w[v] = q[v] * inv;
+    return inv;
 }
+
+static void prim(const Ctx *x, const double *q, double *w) { (void)prim_inv(x, q, w); }
 
 static void cons(const Ctx *x, const double *w, double *q)
 {
@@ -247,15 +251,16 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
     x.gm1 = gm1;
     x.inv_gm1 = 1.0 / gm1;
     double wL[MAXV], wR[MAXV], fL[MAXV], fR[MAXV];
-    prim(&x, qL, wL);
-    prim(&x, qR, wR);
+    double iL = prim_inv(&x, qL, wL);
+    double iR = prim_inv(&x, qR, wR);
     phys_flux(nvar, d, wL, qL, fL);
     phys_flux(nvar, d, wR, qR, fR);
     double rL = wL[0], rR = wR[0];
     double uL = wL[1 + d], uR = wR[1 + d];
     double pL = wL[4], pR = wR[4];
-    double cL = sqrt(gamma * pL / rL);
-    double cR = sqrt(gamma * pR / rR);
+    /* c_s = sqrt(gamma P / rho) (eq. eos_gas), with the reciprocal density formed above */
+    double cL = sqrt(gamma * pL * iL);
+    double cR = sqrt(gamma * pR * iR);
     double SL = fmin(uL - cL, uR - cR);
     double SR = fmax(uL + cL, uR + cR);
     if (SL >= 0.0) {
@@ -279,11 +284,11 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
     double mR = rR * (SR - uR);
     double Ss = (pR - pL + uL * mL - uR * mR) / (mL - mR);
     const double *q, *w, *f;
-    double S, m;
+    double S, m, iv;
     if (Ss >= 0.0) {
-        q = qL; w = wL; f = fL; S = SL; m = mL;
+        q = qL; w = wL; f = fL; S = SL; m = mL; iv = iL;
     } else if (SR > 0.0) {
-        q = qR; w = wR; f = fR; S = SR; m = mR;
+        q = qR; w = wR; f = fR; S = SR; m = mR; iv = iR;
     } else {
         for (int v = 0; v < nvar; v++)
             F[v] = fR[v];
@@ -297,7 +302,7 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
     us[2] = fac * w[2];
     us[3] = fac * w[3];
     us[1 + d] = fac * Ss;
-    us[4] = fac * (q[4] / w[0] + (Ss - un) * (Ss + w[4] / m));
+    us[4] = fac * (q[4] * iv + (Ss - un) * (Ss + w[4] / m));
     for (int v = 5; v < nvar; v++)
         us[v] = fac * w[v];
     for (int v = 0; v < nvar; v++)
@@ -563,6 +568,14 @@ static void grav_source(const Ctx *x, const double *q, const double g[3], double
     S[4] = q[1] * g[0] + q[2] * g[1] + q[3] * g[2];
 }
 
+/* rho > 0 and P > 0; for rho > 0 the latter is e = E - |m|^2/(2 rho) > 0, tested as
+ * 2 rho E - |m|^2 > 0 */
+static int positive_state(const double *q)
+{
+    double m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    return q[0] > 0.0 && 2.0 * q[0] * q[4] - m2 > 0.0;
+}
+
 static int nonphysical(const Ctx *x, const double *q)
 {
     for (int v = 0; v < x->nvar; v++)
@@ -715,8 +728,7 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                         a[v] = um[d][v] + du[v];
                         b[v] = up[d][v] + du[v];
                     }
-                    if (!(a[0] > 0.0) || !(pressure_of(&x, a) > 0.0) || !(b[0] > 0.0) ||
-                        !(pressure_of(&x, b) > 0.0))
+                    if (!positive_state(a) || !positive_state(b))
                         bad = 1;
                 }
                 if (bad) {
@@ -886,8 +898,8 @@ int or_compute_dt(const or_config *c, const double *U, double *dt)
                     bad = 1;
                     continue;
                 }
-                prim(&x, q, w);
-                double cs = sqrt(c->gamma * w[4] / w[0]);
+                double inv = prim_inv(&x, q, w);
+                double cs = sqrt(c->gamma * w[4] * inv);
                 double s = 0.0;
                 for (int d = 0; d < 3; d++)
                     if (x.act[d])

@@ -1,8 +1,9 @@
 """Build libhydro.so (gfx950) in-tree with hipcc.
 
 Each HIP translation unit is compiled separately (no relocatable device code):
-  hx_sweep_fp64.hip  FP64 sweep, -ffp-contract=off so its rounding matches the FP64 oracle
-  hx_sweep_fp32.hip  FP32-form sweep (contraction allowed)
+  hx_sweep_fp64*.hip FP64 sweep, -ffp-contract=off so its rounding matches the FP64 oracle
+  hx_sweep_fp32*.hip FP32-form sweep (contraction allowed)
+  (the *_hllc_vl units fix HLLC + van Leer at compile time; the others take them at run time)
   hx_reduce.hip      dt / totals / enclosed-mass reductions, -ffp-contract=off
   hx_abi.hip         C ABI host code
 Packed FP32 instructions are disabled for all device code.
@@ -27,7 +28,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.
           "-Wno-unused-command-line-argument"]
 UNITS = {
     "hx_sweep_fp64.hip": ["-ffp-contract=off"],
+    "hx_sweep_fp64_hllc_vl.hip": ["-ffp-contract=off"],
     "hx_sweep_fp32.hip": [],
+    "hx_sweep_fp32_hllc_vl.hip": [],
     "hx_reduce.hip": ["-ffp-contract=off"],
     "hx_abi.hip": ["-ffp-contract=off"],
 }

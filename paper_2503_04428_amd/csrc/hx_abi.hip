@@ -72,7 +72,7 @@ struct Layout {
     size_t state[2];
     size_t tab[3][3];  // cm, cp, w per axis
     size_t rabs, sabs, rf, vr, hr, ct, sf;
-    size_t gr, menc, shell, partial, dt, flag, tot, mlp;
+    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp;
     size_t total;
     int ntab[3];
     int nchunk, nred;
@@ -179,6 +179,8 @@ Layout layout(const hx_config* c)
     long long nb = (nc + 255) / 256;
     L.nred = (int)(nb < MAX_RED_BLOCKS ? nb : MAX_RED_BLOCKS);
     L.partial = take(sizeof(double) * (size_t)L.nred * (nv > 1 ? nv : 1));
+    // per-workgroup CFL maxima written by the sweep, sized for the smallest z chunk
+    L.dtpart = take(sizeof(double) * (size_t)hx::sweep_nblocks(c->ndim, c->n, 1));
     L.dt = take(sizeof(double));
     L.flag = take(sizeof(int));
     L.tot = take(sizeof(double) * nv);
@@ -208,6 +210,8 @@ struct hx_ctx {
     hx::Geo geo;
     int kz = 32;
     double scale = 0.0;  // 4 pi / Omega_w
+    bool dtpart_valid = false;  // the sweep's CFL maxima describe the current state
+    long long dtpart_nb = 0;
 };
 
 namespace {
@@ -383,13 +387,22 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     p.gr = at<double>(x, x->L.gr);
     p.geo = x->geo;
     p.flag = at<int>(x, x->L.flag);
+    p.dtpart = at<double>(x, x->L.dtpart);
     p.kz = c.ndim == 3 ? (x->kz < c.n[2] ? x->kz : c.n[2]) : 1;
     p.mlp = at<float>(x, x->L.mlp);
-    hipError_t e = x->fp32 ? hx::launch_sweep_fp32(p, c.ndim, x->nvar, c.geom, x->stream)
-                           : hx::launch_sweep_fp64(p, c.ndim, x->nvar, c.geom, x->stream);
+    const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC;
+    hipError_t e;
+    if (x->fp32)
+        e = spec ? hx::launch_sweep_fp32_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream)
+                 : hx::launch_sweep_fp32_generic(p, c.ndim, x->nvar, c.geom, x->stream);
+    else
+        e = spec ? hx::launch_sweep_fp64_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream)
+                 : hx::launch_sweep_fp64_generic(p, c.ndim, x->nvar, c.geom, x->stream);
     if (e != hipSuccess)
         return fail(HX_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     x->cur = 1 - x->cur;
+    x->dtpart_valid = true;
+    x->dtpart_nb = hx::sweep_nblocks(c.ndim, c.n, p.kz);
     return HX_OK;
 }
 
@@ -481,6 +494,7 @@ hx_status hx_set_state(hx_ctx* x, const double* d_U)
     }
     x->cur = 0;
     x->have_state = true;
+    x->dtpart_valid = false;
     clear_flag_kernel<<<1, 1, 0, x->stream>>>(at<int>(x, x->L.flag));
     HIPCHECK(hipGetLastError());
     return HX_OK;
@@ -507,6 +521,11 @@ hx_status hx_compute_dt_device(hx_ctx* x, double* d_dt)
         return fail(HX_EINVAL, "null argument");
     if (!x->have_state)
         return fail(HX_ESTATE, "no state loaded");
+    if (x->dtpart_valid) {
+        // the last sweep already reduced the CFL rate of the state it wrote, per workgroup
+        HIPCHECK(hx::launch_dt_final(at<double>(x, x->L.dtpart), (int)x->dtpart_nb, x->cfg.cfl, d_dt, x->stream));
+        return HX_OK;
+    }
     hx::DtParams p = dt_params(x);
     HIPCHECK(hx::launch_dt(p, x->fp32, x->L.nred, x->cfg.cfl, d_dt, x->stream));
     return HX_OK;

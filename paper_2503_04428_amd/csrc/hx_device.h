@@ -44,7 +44,7 @@ struct PrimImpl;
 
 template <int NV>
 struct PrimImpl<double, NV> {
-    static __device__ __forceinline__ void run(const Gas<double>& g, const double* q, double* w)
+    static __device__ __forceinline__ double run(const Gas<double>& g, const double* q, double* w)
     {
         double rho = q[0];
         double inv = 1.0 / rho;
@@ -58,6 +58,7 @@ struct PrimImpl<double, NV> {
 #pragma unroll
         for (int v = 5; v < NV; v++)
             w[v] = q[v] * inv;
+        return inv;
     }
 };
 
@@ -65,7 +66,7 @@ template <int NV>
 struct PrimImpl<float, NV> {
     // FP32 bulk, FP64 island for the internal energy: 1/rho from the hardware reciprocal refined
     // by one FP64 Newton step, then e = E - |m|^2/(2 rho) in FP64.
-    static __device__ __forceinline__ void run(const Gas<float>& g, const float* q, float* w)
+    static __device__ __forceinline__ float run(const Gas<float>& g, const float* q, float* w)
     {
         float rho = q[0];
         float r = __builtin_amdgcn_rcpf(rho);
@@ -82,13 +83,23 @@ struct PrimImpl<float, NV> {
 #pragma unroll
         for (int v = 5; v < NV; v++)
             w[v] = q[v] * inv;
+        return inv;
     }
 };
 
+// returns the reciprocal density used for the velocities
 template <typename R, int NV>
-__device__ __forceinline__ void to_prim(const Gas<R>& g, const R* q, R* w)
+__device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w)
 {
-    PrimImpl<R, NV>::run(g, q, w);
+    return PrimImpl<R, NV>::run(g, q, w);
+}
+
+// rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division)
+template <typename R>
+__device__ __forceinline__ bool positive_state(const R* q)
+{
+    R m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    return q[0] > R(0) && R(2) * q[0] * q[4] - m2 > R(0);
 }
 
 template <typename R, int NV>
@@ -128,15 +139,15 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
 {
     using N = Num<R>;
     R wL[NV], wR[NV], fL[NV], fR[NV];
-    to_prim<R, NV>(g, qL, wL);
-    to_prim<R, NV>(g, qR, wR);
+    const R iL = to_prim<R, NV>(g, qL, wL);
+    const R iR = to_prim<R, NV>(g, qR, wR);
     phys_flux<R, NV, D>(wL, qL, fL);
     phys_flux<R, NV, D>(wR, qR, fR);
     R rL = wL[0], rR = wR[0];
     R uL = wL[1 + D], uR = wR[1 + D];
     R pL = wL[4], pR = wR[4];
-    R cL = N::sqrt_(N::div(g.gamma * pL, rL));
-    R cR = N::sqrt_(N::div(g.gamma * pR, rR));
+    R cL = N::sqrt_(g.gamma * pL * iL);
+    R cR = N::sqrt_(g.gamma * pR * iR);
     R SL = fmin(uL - cL, uR - cR);
     R SR = fmax(uL + cL, uR + cR);
     if (SL >= R(0)) {
@@ -170,6 +181,7 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
     const bool left = Ss >= R(0);
     R S = left ? SL : SR;
     R m = left ? mL : mR;
+    R iv = left ? iL : iR;
     R us[NV];
     // select the star side through registers (no pointer selects, everything stays in VGPRs)
     R qs[NV], ws[NV], fs[NV];
@@ -186,7 +198,7 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
     us[2] = fac * ws[2];
     us[3] = fac * ws[3];
     us[1 + D] = fac * Ss;
-    us[4] = fac * (N::div(qs[4], ws[0]) + (Ss - un) * (Ss + N::div(ws[4], m)));
+    us[4] = fac * (qs[4] * iv + (Ss - un) * (Ss + N::div(ws[4], m)));
 #pragma unroll
     for (int v = 5; v < NV; v++)
         us[v] = fac * ws[v];
@@ -208,6 +220,29 @@ __device__ __forceinline__ R limit(int lim, R a, R b)
     if (lim == HX_LIM_VANALBADA)
         return N::div(a * b * (a + b), a * a + b * b);
     return N::div(R(2) * a * b, a + b);
+}
+
+// 16-lane row shifts (DPP row_shr:1 / row_shl:1): lane l of each row of 16 receives the value of
+// lane l-1 (l+1); the first (last) lane of a row keeps its own value
+__device__ __forceinline__ int dpp_shr1_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_shl1_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x101, 0xF, 0xF, false); }
+
+template <bool UP>
+__device__ __forceinline__ double row_shift(double v)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    int lo = (int)(unsigned)(u & 0xffffffffull), hi = (int)(unsigned)(u >> 32);
+    lo = UP ? dpp_shr1_i(lo) : dpp_shl1_i(lo);
+    hi = UP ? dpp_shr1_i(hi) : dpp_shl1_i(hi);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <bool UP>
+__device__ __forceinline__ float row_shift(float v)
+{
+    int i = __float_as_int(v);
+    i = UP ? dpp_shr1_i(i) : dpp_shl1_i(i);
+    return __int_as_float(i);
 }
 
 // boundary image of index i on an axis with n cells; indices are first clamped into the

@@ -35,8 +35,11 @@ struct ShellParams {
     double G, Mc;
 };
 
-hipError_t launch_sweep_fp64(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
-hipError_t launch_sweep_fp32(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_sweep_fp64_generic(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_sweep_fp64_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_sweep_fp32_generic(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_sweep_fp32_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+hipError_t launch_dt_final(const double* partial, int nb, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_dt(const DtParams& p, bool fp32, int nblocks, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_totals(const DtParams& p, bool fp32, int nblocks, double* out, hipStream_t s);
 hipError_t launch_shell(const ShellParams& p, bool fp32, int nchunk, hipStream_t s);
@@ -52,5 +55,11 @@ inline dim3 sweep_grid(int ndim, const int n[3], int kz)
     return dim3((n[0] + 13) / 14, (n[1] + 13) / 14, (n[2] + kz - 1) / kz);
 }
 inline dim3 sweep_block(int ndim) { return ndim == 1 ? dim3(64, 1, 1) : dim3(16, 16, 1); }
+
+inline long long sweep_nblocks(int ndim, const int n[3], int kz)
+{
+    dim3 g = sweep_grid(ndim, n, kz);
+    return (long long)g.x * g.y * g.z;
+}
 
 }  // namespace hx

@@ -59,7 +59,8 @@ struct SweepParams {
     double g0[3];
     const double* gr;    // radial acceleration per interior r index (point / monopole)
     Geo geo;
-    int* flag;           // set to 1 when a non-physical U^n is met
+    int* flag;           // set to 1 when a non-physical state is met
+    double* dtpart;      // per-workgroup maximum CFL rate of U^{n+1}
     int kz;              // z planes per block (3D)
     const float* mlp;    // learned limiter weights (FP32 master copy)
 };

@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(RB) dt_partial_kernel(const DtParams p)
             bad = 1;
             continue;
         }
-        double cs = sqrt(p.gamma * pr / rho);
+        double cs = sqrt(p.gamma * pr * inv);
         double u[3] = {u1, u2, u3};
         double s = 0.0;
         for (int d = 0; d < p.ndim; d++) {
@@ -237,6 +237,12 @@ hipError_t launch_dt(const DtParams& p, bool fp32, int nblocks, double cfl, doub
     else
         dt_partial_kernel<double><<<nblocks, RB, 0, s>>>(p);
     dt_final_kernel<<<1, RB, 0, s>>>(p.partial, nblocks, cfl, dt_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_final(const double* partial, int nb, double cfl, double* dt_out, hipStream_t s)
+{
+    dt_final_kernel<<<1, RB, 0, s>>>(partial, nb, cfl, dt_out);
     return hipGetLastError();
 }
 

@@ -34,16 +34,6 @@ struct Tile<3> {
     static constexpr int BX = 16, BY = 16;
 };
 
-template <typename R>
-__device__ __forceinline__ R shfl_up1(R v, int width)
-{
-    return __shfl_up(v, 1, width);
-}
-template <typename R>
-__device__ __forceinline__ R shfl_dn1(R v, int width)
-{
-    return __shfl_down(v, 1, width);
-}
 
 // Load U^n of one (possibly ghost) cell with boundary images applied.
 template <typename R, int NV>
@@ -72,7 +62,55 @@ __device__ __forceinline__ bool bad_state(const R* q, const R* w)
     return bad;
 }
 
-template <typename R, int NV, int NDIM, int GEOM>
+// x-neighbour exchange inside 16-lane rows (DPP) or, for 64-wide 1D tiles, across the wave
+template <int BX, typename R>
+__device__ __forceinline__ R from_left(R v)
+{
+    if constexpr (BX == 16)
+        return row_shift<true>(v);
+    else
+        return __shfl_up(v, 1, BX);
+}
+template <int BX, typename R>
+__device__ __forceinline__ R from_right(R v)
+{
+    if constexpr (BX == 16)
+        return row_shift<false>(v);
+    else
+        return __shfl_down(v, 1, BX);
+}
+
+// CFL signal rate sum_d (|u_d| + c_s)/dx_d of a conserved state, in FP64, in the operation order
+// of the reference definition; returns a negative value for a non-physical state
+template <typename R, int NV, int NDIM>
+__device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const double* wd)
+{
+    double q[NV];
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        q[v] = (double)acc[v];
+        fin = fin && isfinite(q[v]);
+    }
+    const double rho = q[0];
+    const double inv = 1.0 / rho;
+    const double u1 = q[1] * inv, u2 = q[2] * inv, u3 = q[3] * inv;
+    const double ke = 0.5 * (q[1] * u1 + q[2] * u2 + q[3] * u3);
+    const double pr = (gamma - 1.0) * (q[4] - ke);
+    if (!fin || !(rho > 0.0) || !(pr > 0.0))
+        return -1.0;
+    const double cs = sqrt(gamma * pr * inv);
+    const double u[3] = {u1, u2, u3};
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; d++)
+        s += (fabs(u[d]) + cs) / wd[d];
+    return s;
+}
+
+// SPEC = 1 compiles the common HLLC + van Leer case with both choices fixed; SPEC = 0 reads the
+// limiter and the Riemann solver from the parameters.
+template <typename R, int NV, int NDIM, int GEOM, int SPEC>
 __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     sweep_kernel(const SweepParams p)
 {
@@ -90,6 +128,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     __shared__ R sW[NSLOT][NV][RY * RX];  // primitives of a plane incl. a 2-cell ring
     __shared__ R sFy[NV][NYB];            // +y half-step state of every predictor cell
     __shared__ R sGy[NV][NYB];            // y flux through the lower face of every cell
+    __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
+    const int lim = SPEC ? HX_LIM_VANLEER : p.limiter;
+    const int solver = SPEC ? HX_HLLC : p.riemann;
+    double smax = 0.0;     // CFL rate of the cells this thread stores
 
     const R* __restrict__ U = (const R*)p.U;
     R* __restrict__ Un = (R*)p.Unew;
@@ -157,55 +199,88 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     }
 
     // ------------------------------------------------------------------ plane loader
-    // writes primitives of the (RX x RY) rectangle of plane k into slot s and returns the
-    // conserved state of this thread's own cell of that plane
-    auto load_plane = [&](int k, int s, R* qown, R* wown) {
-        bool fk = false;
-        const int kk = NDIM == 3 ? bc_image(k, n2, ng, p.bc[2][0], p.bc[2][1], fk) : 0;
+    // The primitives of the (RX x RY) rectangle of a plane go to LDS.  Each thread loads its own
+    // cell (rectangle position (tx+1, ty+1)); the ring around the tile has fewer cells than the
+    // block has threads, so a thread loads at most one ring cell.  Loading is split in two halves:
+    // issue_plane() starts the global loads, commit_plane() converts and stores them, so the loads of
+    // plane k+1 are in flight while the x and y parts of the predictor of plane k run.
+    constexpr int NRING = NDIM >= 2 ? 2 * RX + 2 * BY : 2;
+    static_assert(NRING <= NT, "at most one ring cell per thread");
+    const bool has_ring = tid < NRING;
+    int ring_lds = 0, ri = 0, rj = 0;
+    bool rf0 = false, rf1 = false;
+    if (has_ring) {
+        int lx, ly;
+        if (NDIM >= 2) {
+            if (tid < RX) {
+                lx = tid;
+                ly = 0;
+            } else if (tid < 2 * RX) {
+                lx = tid - RX;
+                ly = RY - 1;
+            } else if (tid < 2 * RX + BY) {
+                lx = 0;
+                ly = tid - 2 * RX + 1;
+            } else {
+                lx = RX - 1;
+                ly = tid - 2 * RX - BY + 1;
+            }
+        } else {
+            lx = tid == 0 ? 0 : RX - 1;
+            ly = 0;
+        }
+        ri = bc_image(x0 - 2 + lx, n0, ng, p.bc[0][0], p.bc[0][1], rf0);
+        if (NDIM >= 2)
+            rj = bc_image(y0 - 2 + ly, n1, ng, p.bc[1][0], p.bc[1][1], rf1);
+        ring_lds = ly * RX + lx;
+    }
+    const int own = (NDIM >= 2 ? (ty + 1) * RX : 0) + tx + 1;
+
+    auto raw_load = [&](int i0, int j0, int kk, R* q) {
+        const long long off = ((long long)kk * n1 + j0) * n0 + i0;
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            q[v] = U[(long long)v * p.plane + off];
+    };
+    auto plane_image = [&](int k, bool& fk) {
+        fk = false;
+        return NDIM == 3 ? bc_image(k, n2, ng, p.bc[2][0], p.bc[2][1], fk) : 0;
+    };
+    auto issue_plane = [&](int k, R* qown, R* qring) {
+        bool fk;
+        const int kk = plane_image(k, fk);
+        raw_load(ii, jj, kk, qown);
+        if (has_ring)
+            raw_load(ri, rj, kk, qring);
+    };
+    auto commit_plane = [&](int k, int s, R* qown, R* wown, R* qring) {
+        bool fk;
+        (void)plane_image(k, fk);
         const bool kin = NDIM < 3 || (k >= 0 && k < n2);
-        // own cell: rectangle position (tx + 1, ty + 1)
-        fetch_cell<R, NV>(p, U, ii, jj, kk, fx, fy, fk, qown);
+        if (fx)
+            qown[1] = -qown[1];
+        if (fy)
+            qown[2] = -qown[2];
+        if (fk)
+            qown[3] = -qown[3];
         to_prim<R, NV>(gas, qown, wown);
-        const int own = (NDIM >= 2 ? (ty + 1) * RX : 0) + tx + 1;
 #pragma unroll
         for (int v = 0; v < NV; v++)
             sW[s][v][own] = wown[v];
         if (kin && interior && bad_state<R, NV>(qown, wown))
             p.flag[0] = 1;
-        // ring of the rectangle
-        constexpr int NRING = NDIM >= 2 ? 2 * RX + 2 * BY : 2;
-        for (int r = tid; r < NRING; r += NT) {
-            int lx, ly;
-            if (NDIM >= 2) {
-                if (r < RX) {
-                    lx = r;
-                    ly = 0;
-                } else if (r < 2 * RX) {
-                    lx = r - RX;
-                    ly = RY - 1;
-                } else if (r < 2 * RX + BY) {
-                    lx = 0;
-                    ly = r - 2 * RX + 1;
-                } else {
-                    lx = RX - 1;
-                    ly = r - 2 * RX - BY + 1;
-                }
-            } else {
-                lx = r == 0 ? 0 : RX - 1;
-                ly = 0;
-            }
-            bool f0, f1 = false;
-            const int gi = x0 - 2 + lx;
-            const int ri = bc_image(gi, n0, ng, p.bc[0][0], p.bc[0][1], f0);
-            int rj = 0;
-            if (NDIM >= 2)
-                rj = bc_image(y0 - 2 + ly, n1, ng, p.bc[1][0], p.bc[1][1], f1);
-            R q[NV], w[NV];
-            fetch_cell<R, NV>(p, U, ri, rj, kk, f0, f1, fk, q);
-            to_prim<R, NV>(gas, q, w);
+        if (has_ring) {
+            if (rf0)
+                qring[1] = -qring[1];
+            if (rf1)
+                qring[2] = -qring[2];
+            if (fk)
+                qring[3] = -qring[3];
+            R w[NV];
+            to_prim<R, NV>(gas, qring, w);
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                sW[s][v][ly * RX + lx] = w[v];
+                sW[s][v][ring_lds] = w[v];
         }
     };
 
@@ -230,7 +305,6 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     for (int v = 0; v < 6; v++)
         sph_t[v] = 0.0;
 
-    const int own = (NDIM >= 2 ? (ty + 1) * RX : 0) + tx + 1;
     int kbeg = k0, kend = k0;  // loop bounds over predictor planes
     if (NDIM == 3) {
         kbeg = k0 - 1;
@@ -238,23 +312,27 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
         // own column at k0-2 (z neighbour of the first predictor plane) and plane k0-1
         bool fk;
         const int kk = bc_image(k0 - 2, n2, ng, p.bc[2][0], p.bc[2][1], fk);
-        R q[NV];
+        R q[NV], qr[NV];
         fetch_cell<R, NV>(p, U, ii, jj, kk, fx, fy, fk, q);
         to_prim<R, NV>(gas, q, wprev);
-        load_plane(k0 - 1, (k0 - 1) & 1, qcur, wcur);
+        issue_plane(k0 - 1, qcur, qr);
+        commit_plane(k0 - 1, (k0 - 1) & 1, qcur, wcur, qr);
         // a valid state for the (unused) z flux below the first predictor plane
 #pragma unroll
         for (int v = 0; v < NV; v++)
             uzp[v] = qcur[v];
     } else {
-        load_plane(0, 0, qcur, wcur);
+        R qr[NV];
+        issue_plane(0, qcur, qr);
+        commit_plane(0, 0, qcur, wcur, qr);
     }
     __syncthreads();
 
     for (int k = kbeg; k <= kend; ++k) {
         const int slot = NDIM == 3 ? (k & 1) : 0;
+        R qring[NV];
         if (NDIM == 3)
-            load_plane(k + 1, (k + 1) & 1, qnext, wnext);
+            issue_plane(k + 1, qnext, qring);
 
         // -------------------------------------------------------------- predictor, plane k
         bool fzk = false;
@@ -286,7 +364,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
             for (int v = 0; v < NV; v++) {
                 R a = cmx * (wcur[v] - sW[slot][v][own - 1]);
                 R b = cpx * (sW[slot][v][own + 1] - wcur[v]);
-                R d = limit<R>(p.limiter, a, b);
+                R d = limit<R>(lim, a, b);
                 dlt[0][v] = d;
                 wm[v] = wcur[v] - d;
                 wp[v] = wcur[v] + d;
@@ -305,7 +383,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
             for (int v = 0; v < NV; v++) {
                 R a = cmy * (wcur[v] - sW[slot][v][own - RX]);
                 R b = cpy * (sW[slot][v][own + RX] - wcur[v]);
-                R d = limit<R>(p.limiter, a, b);
+                R d = limit<R>(lim, a, b);
                 dlt[1][v] = d;
                 wm[v] = wcur[v] - d;
                 wp[v] = wcur[v] + d;
@@ -319,12 +397,13 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
                 du[v] += lamy * (fm[v] - fp[v]);
         }
         if (NDIM == 3) {
+            commit_plane(k + 1, (k + 1) & 1, qnext, wnext, qring);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 R a = cmz * (wcur[v] - wprev[v]);
                 R b = cpz * (wnext[v] - wcur[v]);
-                R d = limit<R>(p.limiter, a, b);
+                R d = limit<R>(lim, a, b);
                 dlt[2][v] = d;
                 wm[v] = wcur[v] - d;
                 wp[v] = wcur[v] + d;
@@ -359,7 +438,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
         for (int d = 0; d < NDIM; d++) {
 #pragma unroll
             for (int side = 0; side < 2; side++) {
-                R ws[NV], qs[NV], wq[NV];
+                R ws[NV], qs[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ws[v] = side ? wcur[v] + dlt[d][v] : wcur[v] - dlt[d][v];
@@ -367,8 +446,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     qs[v] += du[v];
-                to_prim<R, NV>(gas, qs, wq);
-                bad = bad || !(qs[0] > R(0)) || !(wq[4] > R(0));
+                bad = bad || !positive_state<R>(qs);
             }
         }
         if (bad) {
@@ -422,26 +500,26 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
             R L[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                L[v] = shfl_up1(qpx[v], BX);
+                L[v] = from_left<BX>(qpx[v]);
             if (tx == 0) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     L[v] = qmx[v];
             }
-            riemann<R, NV, 0>(p.riemann, gas, L, qmx, Fx);
+            riemann<R, NV, 0>(solver, gas, L, qmx, Fx);
         }
         if (NDIM >= 2) {
             R L[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 L[v] = ty > 0 ? sFy[v][tid - BX] : qmy[v];
-            riemann<R, NV, 1>(p.riemann, gas, L, qmy, Fy);
+            riemann<R, NV, 1>(solver, gas, L, qmy, Fy);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 sGy[v][tid] = Fy[v];
         }
         if (NDIM == 3) {
-            riemann<R, NV, 2>(p.riemann, gas, uzp, qmz, Fz);
+            riemann<R, NV, 2>(solver, gas, uzp, qmz, Fz);
         }
         __syncthreads();
 
@@ -449,7 +527,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
         R Fxr[NV], Fyu[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++)
-            Fxr[v] = shfl_dn1(Fx[v], BX);
+            Fxr[v] = from_right<BX>(Fx[v]);
         if (NDIM >= 2) {
 #pragma unroll
             for (int v = 0; v < NV; v++)
@@ -490,6 +568,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     Un[(long long)v * p.plane + off] = acc[v];
+                double wd[3] = {wx, wy, GEOM == HX_CART ? p.geo.w[2][kp + ng]
+                                                        : p.geo.rabs[gx] * p.geo.sabs[gy] * p.geo.w[2][kp + ng]};
+                const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
+                if (sr < 0.0)
+                    p.flag[0] = 1;
+                smax = fmax(smax, sr);
             }
             if (plane_live) {
                 // x and y terms of plane k
@@ -589,6 +673,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         Un[(long long)v * p.plane + off] = acc[v];
+                    double wd[3] = {wx, wy, 0.0};
+                    const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
+                    if (sr < 0.0)
+                        p.flag[0] = 1;
+                    smax = fmax(smax, sr);
                 }
             }
         }
@@ -602,6 +691,21 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
                 qcur[v] = qnext[v];
             }
         }
+    }
+
+    // per-block maximum of the CFL rate of the stored cells (the time step of the next step)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        smax = fmax(smax, __shfl_xor(smax, o, 64));
+    if ((tid & 63) == 0)
+        sRed[tid >> 6] = smax;
+    __syncthreads();
+    if (tid == 0) {
+        double m = sRed[0];
+        for (int w = 1; w < NT / 64; w++)
+            m = fmax(m, sRed[w]);
+        const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        p.dtpart[b] = m;
     }
 }
 

@@ -1,0 +1,13 @@
+// FP64 instantiations of the fused sweep.  Built with -ffp-contract=off so that every
+// expression rounds exactly like the FP64 CPU oracle's.
+// HLLC + van Leer, fixed at compile time.
+#include "hx_sweep_inst.h"
+
+namespace hx {
+
+hipError_t launch_sweep_fp64_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s)
+{
+    return launch_sweep_t<double, 1>(p, ndim, nvar, geom, s);
+}
+
+}  // namespace hx
