@@ -9,8 +9,10 @@ HBM before the timed region starts.
 Prints one JSON line (see the contract in the repository's documentation).  The roofline block
 refers to the dominant kernel, the fused sweep: algorithmic bytes per launch = 2 * nvar * b * cells
 (U^n read once, U^{n+1} written once), divided by the sweep's average duration measured with HIP
-events on the stream it runs on.  The cpu_baseline block times the FP64 oracle (single-threaded,
-as it stands) on a bounded slab of the same first step.
+events on the stream it runs on; roofline.traffic is the measured HBM bytes per launch (rocprofv3
+FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy, recorded in profiles/) over the same duration,
+reported only while the kernel sources match the recorded ones.  The cpu_baseline block times the
+FP64 oracle (single-threaded, as it stands) on a bounded slab of the same first step.
 """
 from __future__ import annotations
 
@@ -69,6 +71,24 @@ def run_form(hydro, torch, prob, form, steps, warmup, zchunk):
     return out
 
 
+def recorded_traffic(form):
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE record, valid
+    only while the kernel sources are the ones the counters were taken on (else None)."""
+    from paper_2503_04428_amd.srchash import kernel_source_hash
+
+    path = os.path.join(ROOT, "profiles", "sweep_sedov256_hbm_traffic.md")
+    try:
+        for line in open(path):
+            if "TRAFFIC_JSON" in line:
+                rec = json.loads(line.split("TRAFFIC_JSON", 1)[1])
+                if rec.get("source_hash") != kernel_source_hash():
+                    return None
+                return rec.get(f"{form}_bytes")
+    except OSError:
+        return None
+    return None
+
+
 def cpu_baseline(prob, nz_slab):
     """FP64 oracle (single-threaded C, as it stands) on an nx*ny*nz_slab slab of the first step."""
     import numpy as np
@@ -98,6 +118,8 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -158,6 +180,19 @@ def main():
     if l1 is not None:
         forms["fp32"]["l1_rel_vs_fp64_per_field"] = l1
 
+    if args.copy_ref_mib > 0:
+        nb = args.copy_ref_mib * 1024 * 1024
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
+        del src, dst
+
+    traffic_bytes = recorded_traffic(head["form"]) if args.n == 256 else None
+    traffic = traffic_bytes / (head["sweep_ms_avg"] * 1e-3) / 1e9 if traffic_bytes else None
+
     cpu = None
     if args.cpu_slab > 0:
         log("timing the CPU oracle ...")
@@ -180,7 +215,8 @@ def main():
         "config": {"workload": f"sedov3d-{args.n}^3 (5 conserved + 2 passive scalars, HLLC, van Leer, CFL 0.5)",
                    "cells": cells, "nvar": nvar, "form": head["form"], "dt": "CFL, on device every step"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "hx::sweep_kernel (fused MUSCL-Hancock sweep)",
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,

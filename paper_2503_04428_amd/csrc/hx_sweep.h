@@ -137,8 +137,22 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     R* __restrict__ Un = (R*)p.Unew;
     const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2], ng = p.ng;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
-    const int x0 = blockIdx.x * TX;
-    const int y0 = NDIM >= 2 ? blockIdx.y * TY : 0;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs by linear id, so the
+    // linear id is remapped to give every XCD one contiguous band of tiles (x fastest, then y,
+    // then the z chunk); neighbouring tiles then share their halo planes in the same L2.
+    int bx, by, bz;
+    {
+        const unsigned gx = gridDim.x, gy = gridDim.y;
+        const unsigned nb = gx * gy * gridDim.z;
+        const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+        const unsigned xcd = b % 8u, idx = b / 8u, q = nb / 8u, r = nb % 8u;
+        const unsigned L = xcd * q + (xcd < r ? xcd : r) + idx;
+        bx = (int)(L % gx);
+        by = (int)((L / gx) % gy);
+        bz = (int)(L / (gx * gy));
+    }
+    const int x0 = bx * TX;
+    const int y0 = NDIM >= 2 ? by * TY : 0;
     // cell of this thread (clamped into the ghost range for ragged tiles)
     const int ic = clamp_ghost(x0 + tx - 1, n0, ng);
     const int jc = NDIM >= 2 ? clamp_ghost(y0 + ty - 1, n1, ng) : 0;
@@ -146,7 +160,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
                           (NDIM < 2 || (ty >= 1 && ty <= TY && (y0 + ty - 1) < n1));
     int k0 = 0, k1 = 1;
     if (NDIM == 3) {
-        k0 = blockIdx.z * p.kz;
+        k0 = bz * p.kz;
         k1 = min(k0 + p.kz, n2);
     }
     const double dtd = p.dt_dev ? p.dt_dev[0] : p.dt_host;
