@@ -130,6 +130,39 @@ hx_status hx_set_zchunk(hx_ctx *ctx, int kz);
  * host; synchronises).  For tests of the enclosed-mass reduction. */
 hx_status hx_enclosed_mass(hx_ctx *ctx, double *h_menc);
 
+/* ---- learned slope limiter (context-free; device pointers; asynchronous on hip_stream) ----
+ * The limiter network maps the four undivided differences of a primitive around a cell,
+ * normalised by their largest magnitude, to phi in (0, 2); the limited slope is phi times the
+ * left difference, replaced by van Leer outside the TVD region 0 <= phi <= min(2, 2r).  It is an
+ * extension of the paper's runtime-selectable limiters (Sect. 3.2), trained on fine FP64 solutions
+ * of the scheme itself. */
+
+/* phi of n stencils: d_w HX_MLP_NPARAM FP32 parameters (used as BF16), d_x [n][4] FP32 inputs,
+ * d_phi [n] FP32 output; BF16 matrix-core evaluation, the same code the fused sweep runs. */
+hx_status hx_mlp_eval(const float *d_w, const float *d_x, long long n, float *d_phi, void *hip_stream);
+
+/* Training samples from a batch of 1D FP64 solutions d_fine [5][nrows][nfine] (rho, m1, m2, m3, E):
+ * one sample per (row, coarse cell, primitive), coarse cells = averages of `ratio` fine cells
+ * (nfine divisible by ratio).  Outputs (FP32, n = nrows*(nfine/ratio)*5): d_x [n][4] normalised
+ * coarse differences, d_a [n] the normalised left difference, d_t [n] the least-squares slope of
+ * the fine primitive across the coarse cell (times the coarse width) normalised alike, d_wt [n]
+ * 1 where the network is used (monotone, non-flat stencil away from the row ends), else 0. */
+hx_status hx_mlp_features(const double *d_fine, int nrows, int nfine, int ratio, double gamma, float *d_x,
+                          float *d_a, float *d_t, float *d_wt, void *hip_stream);
+
+/* Device bytes of the scratch buffer hx_mlp_grad needs for n samples. */
+size_t hx_mlp_grad_workspace_bytes(long long n);
+
+/* FP32 loss L = sum wt (phi a - t)^2 / sum wt and its gradient (HX_MLP_NPARAM values) over n samples,
+ * with the caller's scratch d_work (>= hx_mlp_grad_workspace_bytes(n)). */
+hx_status hx_mlp_grad(const float *d_w, const float *d_x, const float *d_a, const float *d_t, const float *d_wt,
+                      long long n, float *d_grad, float *d_loss, void *d_work, size_t work_bytes,
+                      void *hip_stream);
+
+/* One Adam update of the FP32 master weights d_w with moments d_m, d_v (step counts from 1). */
+hx_status hx_mlp_adam(float *d_w, const float *d_grad, float *d_m, float *d_v, int step, float lr, float beta1,
+                      float beta2, float eps, void *hip_stream);
+
 /* Thread-local text of the last error. */
 const char *hx_last_error(void);
 

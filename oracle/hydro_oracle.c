@@ -924,3 +924,74 @@ void or_totals(const or_config *c, const double *U, double *tot)
         tot[v] = s;
     }
 }
+
+/* ------------------------------------------------------------------ learned-limiter samples */
+
+static void restrict_prim(const double *U, long plane, long row_off, int ratio, int i, double gm1, double *w)
+{
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int f = 0; f < ratio; f++)
+        for (int v = 0; v < 5; v++)
+            q[v] += U[v * plane + row_off + (long)i * ratio + f];
+    for (int v = 0; v < 5; v++)
+        q[v] = q[v] / ratio;
+    double inv = 1.0 / q[0];
+    w[0] = q[0];
+    w[1] = q[1] * inv;
+    w[2] = q[2] * inv;
+    w[3] = q[3] * inv;
+    w[4] = gm1 * (q[4] - 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]));
+}
+
+void or_mlp_features(const double *U, int nrows, int nf, int ratio, double gamma, double *x, double *a,
+                     double *t, double *wt)
+{
+    int nc = nf / ratio;
+    long plane = (long)nrows * nf;
+    double gm1 = gamma - 1.0;
+    for (int row = 0; row < nrows; row++)
+        for (int i = 0; i < nc; i++) {
+            long row_off = (long)row * nf;
+            double W[5][5] = {{0.0}}; /* initialised: gcc 11 -O2 mis-handles it conditionally set */
+            int inside = i >= 2 && i <= nc - 3;
+            if (inside)
+                for (int s = 0; s < 5; s++)
+                    restrict_prim(U, plane, row_off, ratio, i - 2 + s, gm1, W[s]);
+            for (int v = 0; v < 5; v++) {
+                long e = ((long)row * nc + i) * 5 + v;
+                for (int k = 0; k < 4; k++)
+                    x[4 * e + k] = 0.0;
+                a[e] = t[e] = wt[e] = 0.0;
+                if (!inside)
+                    continue;
+                double d[4] = {W[1][v] - W[0][v], W[2][v] - W[1][v], W[3][v] - W[2][v], W[4][v] - W[3][v]};
+                double s = 0.0;
+                for (int k = 0; k < 4; k++)
+                    if (fabs(d[k]) > s)
+                        s = fabs(d[k]);
+                if (!(d[1] * d[2] > 0.0 && s > 0.0))
+                    continue;
+                /* least-squares slope of the fine primitive values at fine-cell offsets f - (ratio-1)/2 */
+                double num = 0.0, den = 0.0, mid = 0.5 * (ratio - 1);
+                for (int f = 0; f < ratio; f++) {
+                    double q[5], w[5];
+                    for (int u = 0; u < 5; u++)
+                        q[u] = U[u * plane + row_off + (long)i * ratio + f];
+                    double inv = 1.0 / q[0];
+                    w[0] = q[0];
+                    w[1] = q[1] * inv;
+                    w[2] = q[2] * inv;
+                    w[3] = q[3] * inv;
+                    w[4] = gm1 * (q[4] - 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]));
+                    num += (f - mid) * w[v];
+                    den += (f - mid) * (f - mid);
+                }
+                double slope = ratio * num / den;
+                for (int k = 0; k < 4; k++)
+                    x[4 * e + k] = d[k] / s;
+                a[e] = d[1] / s;
+                t[e] = slope / s;
+                wt[e] = 1.0;
+            }
+        }
+}

@@ -94,6 +94,15 @@ double or_mlp_slope(const double *w, const double d[4], double cm, double cp);
 double or_mlp_loss_grad(const double *w, int B, const double *x, const double *a, const double *t,
                         const double *wt, double *grad);
 
+/* Training samples of the learned limiter from a batch of 1D fine solutions U [5][nrows][nf]:
+ * for every row, coarse cell i (averages of `ratio` fine cells) and primitive v: x[4] = the four
+ * undivided coarse differences around i over their largest magnitude s, a = left difference / s,
+ * t = least-squares slope of the fine primitive inside i, times the coarse width, / s, wt = 1 where
+ * the network is used (differences on both sides of the same sign, not within 2 cells of a row end),
+ * else all zero.  Outputs have nrows*(nf/ratio)*5 entries (x four times that). */
+void or_mlp_features(const double *U, int nrows, int nf, int ratio, double gamma, double *x, double *a,
+                     double *t, double *wt);
+
 #ifdef __cplusplus
 }
 #endif

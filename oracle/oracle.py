@@ -62,6 +62,8 @@ def lib():
         L.or_mlp_slope.restype = C.c_double
         L.or_mlp_loss_grad.argtypes = [_DP, C.c_int, _DP, _DP, _DP, _DP, _DP]
         L.or_mlp_loss_grad.restype = C.c_double
+        L.or_mlp_features.argtypes = [_DP, C.c_int, C.c_int, C.c_int, C.c_double, _DP, _DP, _DP, _DP]
+        L.or_mlp_features.restype = None
         _lib = L
     return _lib
 
@@ -228,3 +230,23 @@ def mlp_loss_grad(w, x, a, t, wt):
     g = np.zeros(MLP_NPARAM)
     loss = lib().or_mlp_loss_grad(_ptr(w), int(a.size), _ptr(x), _ptr(a), _ptr(t), _ptr(wt), _ptr(g))
     return loss, g
+
+
+def mlp_features(U, ratio: int, gamma: float):
+    """Training samples of a batch of 1D fine solutions U [5][nrows][nf] (see hydro_oracle.h)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _, nrows, nf = U.shape
+    n = nrows * (nf // ratio) * 5
+    x = np.zeros(4 * n)
+    a = np.zeros(n)
+    t = np.zeros(n)
+    wt = np.zeros(n)
+    lib().or_mlp_features(_ptr(U), nrows, nf, ratio, float(gamma), _ptr(x), _ptr(a), _ptr(t), _ptr(wt))
+    return x.reshape(n, 4), a, t, wt
+
+
+def bf16_round(w) -> np.ndarray:
+    """Round FP32 values to the nearest BF16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(w, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = (f + 0x7FFF + ((f >> 16) & 1)) & 0xFFFF0000
+    return f.astype(np.uint32).view(np.float32).astype(np.float64)

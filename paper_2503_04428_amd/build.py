@@ -3,8 +3,10 @@
 Each HIP translation unit is compiled separately (no relocatable device code):
   hx_sweep_fp64*.hip FP64 sweep, -ffp-contract=off so its rounding matches the FP64 oracle
   hx_sweep_fp32*.hip FP32-form sweep (contraction allowed)
-  (the *_hllc_vl units fix HLLC + van Leer at compile time; the others take them at run time)
+  (the *_hllc_vl units fix HLLC + van Leer at compile time; the others take them at run time;
+   hx_sweep_fp32_mlp.hip is the learned-limiter form)
   hx_reduce.hip      dt / totals / enclosed-mass reductions, -ffp-contract=off
+  hx_mlp.hip         learned limiter: BF16-MFMA evaluation, training samples, FP32 training
   hx_abi.hip         C ABI host code
 Packed FP32 instructions are disabled for all device code.
 """
@@ -31,7 +33,9 @@ UNITS = {
     "hx_sweep_fp64_hllc_vl.hip": ["-ffp-contract=off"],
     "hx_sweep_fp32.hip": [],
     "hx_sweep_fp32_hllc_vl.hip": [],
+    "hx_sweep_fp32_mlp.hip": [],
     "hx_reduce.hip": ["-ffp-contract=off"],
+    "hx_mlp.hip": ["-ffp-contract=off"],
     "hx_abi.hip": ["-ffp-contract=off"],
 }
 

@@ -96,8 +96,16 @@ hx_status validate(const hx_config* c)
         return fail(HX_EINVAL, "nghost must be 2 or 3 (got %d)", c->nghost);
     if (c->limiter < HX_LIMITER_NONE || c->limiter > HX_LIMITER_MLP)
         return fail(HX_EINVAL, "unknown limiter %d", c->limiter);
-    if (c->limiter == HX_LIMITER_MLP)
-        return fail(HX_EINVAL, "the learned limiter is not available in this build");
+    if (c->limiter == HX_LIMITER_MLP) {
+        if (c->precision != HX_PRECISION_FP32)
+            return fail(HX_EINVAL, "the learned limiter runs in the FP32 form");
+        if (c->nghost != 3)
+            return fail(HX_EINVAL, "the learned limiter needs nghost = 3");
+        if (c->riemann != HX_RIEMANN_HLLC)
+            return fail(HX_EINVAL, "the learned limiter is built with HLLC");
+        if (c->nscalar > 2)
+            return fail(HX_EINVAL, "the learned limiter supports at most 2 passive scalars");
+    }
     if (c->riemann != HX_RIEMANN_HLL && c->riemann != HX_RIEMANN_HLLC)
         return fail(HX_EINVAL, "unknown Riemann solver %d", c->riemann);
     if (c->precision != HX_PRECISION_FP64 && c->precision != HX_PRECISION_FP32)
@@ -108,8 +116,10 @@ hx_status validate(const hx_config* c)
         const bool act = d < c->ndim;
         if (act && c->n[d] < c->nghost)
             return fail(HX_EINVAL, "axis %d: %d cells, need at least nghost = %d", d, c->n[d], c->nghost);
-        if (!act && c->n[d] != 1)
-            return fail(HX_EINVAL, "inactive axis %d must have n = 1", d);
+        // ndim 1 (Cartesian) may carry a batch of independent rows on axis 1
+        const bool batch_axis = c->ndim == 1 && d == 1 && c->geom == HX_GEOM_CART;
+        if (!act && c->n[d] != 1 && !(batch_axis && c->n[d] >= 1))
+            return fail(HX_EINVAL, "inactive axis %d must have n = 1 (a batch of 1D rows needs Cartesian ndim 1)", d);
         if (!c->faces[d])
             return fail(HX_EINVAL, "faces of axis %d missing", d);
         const int nf = act ? c->n[d] + 1 + 2 * c->nghost : 2;
@@ -283,10 +293,12 @@ void build_geometry(hx_ctx* x, std::vector<double>& h, std::vector<std::pair<siz
         vr[i] = (rp * rp * rp - rm * rm * rm) / 3.0;
         hr[i] = 0.5 * (rp * rp - rm * rm);
     }
+    // a batch of 1D rows has one theta cell's worth of faces; the remaining entries stay 0
+    const int nth = c.ndim >= 2 ? n1 : 1;
     for (int j = 0; j < n1; j++)
-        ct[j] = std::cos(xf(1, j)) - std::cos(xf(1, j + 1));
+        ct[j] = j < nth ? std::cos(xf(1, j)) - std::cos(xf(1, j + 1)) : 0.0;
     for (int j = 0; j <= n1; j++)
-        sf[j] = std::sin(xf(1, j));
+        sf[j] = j <= nth ? std::sin(xf(1, j)) : 0.0;
     push(x->L.rf, rf);
     push(x->L.vr, vr);
     push(x->L.hr, hr);
@@ -294,7 +306,7 @@ void build_geometry(hx_ctx* x, std::vector<double>& h, std::vector<std::pair<siz
     push(x->L.sf, sf);
     // solid angle of the wedge and point-mass gravity (the monopole part is recomputed per step)
     double om_t = 0.0, om_p = 0.0;
-    for (int j = 0; j < n1; j++)
+    for (int j = 0; j < nth; j++)
         om_t += ct[j];
     for (int k = 0; k < c.n[2]; k++)
         om_p += dxc(2, k);
@@ -391,8 +403,12 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     p.kz = c.ndim == 3 ? (x->kz < c.n[2] ? x->kz : c.n[2]) : 1;
     p.mlp = at<float>(x, x->L.mlp);
     const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC;
+    if (c.limiter == HX_LIMITER_MLP && !x->have_mlp)
+        return fail(HX_ESTATE, "the learned limiter needs hx_set_mlp before stepping");
     hipError_t e;
-    if (x->fp32)
+    if (c.limiter == HX_LIMITER_MLP)
+        e = hx::launch_sweep_fp32_mlp(p, c.ndim, x->nvar, c.geom, x->stream);
+    else if (x->fp32)
         e = spec ? hx::launch_sweep_fp32_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream)
                  : hx::launch_sweep_fp32_generic(p, c.ndim, x->nvar, c.geom, x->stream);
     else
@@ -607,6 +623,55 @@ hx_status hx_enclosed_mass(hx_ctx* x, double* h_menc)
     HIPCHECK(hipMemcpyAsync(h_menc, at<double>(x, x->L.menc), sizeof(double) * x->cfg.n[0], hipMemcpyDeviceToHost,
                             x->stream));
     HIPCHECK(hipStreamSynchronize(x->stream));
+    return HX_OK;
+}
+
+hx_status hx_mlp_eval(const float* d_w, const float* d_x, long long n, float* d_phi, void* hip_stream)
+{
+    if (!d_w || !d_x || !d_phi || n < 0)
+        return fail(HX_EINVAL, "invalid argument");
+    if (n == 0)
+        return HX_OK;
+    HIPCHECK(hx::launch_mlp_eval(d_w, d_x, n, d_phi, (hipStream_t)hip_stream));
+    return HX_OK;
+}
+
+hx_status hx_mlp_features(const double* d_fine, int nrows, int nfine, int ratio, double gamma, float* d_x,
+                          float* d_a, float* d_t, float* d_wt, void* hip_stream)
+{
+    if (!d_fine || !d_x || !d_a || !d_t || !d_wt || nrows < 1 || ratio < 2 || nfine < 5 * ratio ||
+        nfine % ratio != 0 || !(gamma > 1.0))
+        return fail(HX_EINVAL, "invalid argument");
+    HIPCHECK(hx::launch_mlp_features(d_fine, nrows, nfine, ratio, gamma, d_x, d_a, d_t, d_wt,
+                                     (hipStream_t)hip_stream));
+    return HX_OK;
+}
+
+size_t hx_mlp_grad_workspace_bytes(long long n)
+{
+    if (n < 1)
+        return 0;
+    return sizeof(float) * (size_t)hx::mlp_grad_blocks(n) * (HX_MLP_NPARAM + 2);
+}
+
+hx_status hx_mlp_grad(const float* d_w, const float* d_x, const float* d_a, const float* d_t, const float* d_wt,
+                      long long n, float* d_grad, float* d_loss, void* d_work, size_t work_bytes, void* hip_stream)
+{
+    if (!d_w || !d_x || !d_a || !d_t || !d_wt || !d_grad || !d_loss || !d_work || n < 1)
+        return fail(HX_EINVAL, "invalid argument");
+    if (work_bytes < hx_mlp_grad_workspace_bytes(n))
+        return fail(HX_ENOSPACE, "scratch of %zu bytes, need %zu", work_bytes, hx_mlp_grad_workspace_bytes(n));
+    HIPCHECK(hx::launch_mlp_grad(d_w, d_x, d_a, d_t, d_wt, n, d_grad, d_loss, (float*)d_work,
+                                 (hipStream_t)hip_stream));
+    return HX_OK;
+}
+
+hx_status hx_mlp_adam(float* d_w, const float* d_grad, float* d_m, float* d_v, int step, float lr, float beta1,
+                      float beta2, float eps, void* hip_stream)
+{
+    if (!d_w || !d_grad || !d_m || !d_v || step < 1)
+        return fail(HX_EINVAL, "invalid argument");
+    HIPCHECK(hx::launch_mlp_adam(d_w, d_grad, d_m, d_v, step, lr, beta1, beta2, eps, (hipStream_t)hip_stream));
     return HX_OK;
 }
 

@@ -124,8 +124,8 @@ __global__ void __launch_bounds__(RB) totals_partial_kernel(const DtParams p)
             const int k = (int)(r / p.n[1]);
             double dV;
             if (p.geom == HX_CART)
-                dV = p.geo.w[0][i + (p.ndim > 0 ? p.ng : 0)] * p.geo.w[1][j + (p.ndim > 1 ? p.ng : 0)] *
-                     p.geo.w[2][k + (p.ndim > 2 ? p.ng : 0)];
+                dV = p.geo.w[0][i + p.ng] * p.geo.w[1][p.ndim > 1 ? j + p.ng : 0] *
+                     p.geo.w[2][p.ndim > 2 ? k + p.ng : 0];
             else
                 dV = p.geo.vr[i] * p.geo.ct[j] * p.geo.w[2][k + (p.ndim > 2 ? p.ng : 0)];
             s += (double)U[(long long)v * ncell + c] * dV;

@@ -16,6 +16,7 @@
 // 1D and 2D use the same code with the inactive axes compiled out.
 #pragma once
 #include "hx_device.h"
+#include "hx_mlp.h"
 
 namespace hx {
 
@@ -108,7 +109,8 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
     return s;
 }
 
-// SPEC = 1 compiles the common HLLC + van Leer case with both choices fixed; SPEC = 0 reads the
+// SPEC = 1 compiles the common HLLC + van Leer case with both choices fixed; SPEC = 2 the learned
+// limiter with HLLC (slope stencil of half-width 2, BF16 matrix-core network); SPEC = 0 reads the
 // limiter and the Riemann solver from the parameters.
 template <typename R, int NV, int NDIM, int GEOM, int SPEC>
 __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
@@ -118,8 +120,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     constexpr int BX = Tile<NDIM>::BX;
     constexpr int BY = Tile<NDIM>::BY;
     constexpr int NT = BX * BY;
-    constexpr int RX = BX + 2;
-    constexpr int RY = NDIM >= 2 ? BY + 2 : 1;
+    constexpr bool MLP = SPEC == 2;
+    constexpr int S = MLP ? 2 : 1;  // half-width of the slope stencil
+    constexpr int RX = BX + 2 * S;
+    constexpr int RY = NDIM >= 2 ? BY + 2 * S : 1;
+    constexpr int NWAVE = NT / 64 > 0 ? NT / 64 : 1;
     constexpr int NSLOT = NDIM == 3 ? 2 : 1;
     constexpr int NYB = NDIM >= 2 ? NT : 1;
     constexpr int TX = BX - 2;
@@ -128,8 +133,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     __shared__ R sW[NSLOT][NV][RY * RX];  // primitives of a plane incl. a 2-cell ring
     __shared__ R sFy[NV][NYB];            // +y half-step state of every predictor cell
     __shared__ R sGy[NV][NYB];            // y flux through the lower face of every cell
-    __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
-    const int lim = SPEC ? HX_LIM_VANLEER : p.limiter;
+    __shared__ double sRed[NWAVE];
+    // learned limiter: per-wave queue of the stencils that need the network, and its outputs
+    __shared__ unsigned long long sQx[MLP ? NWAVE : 1][MLP ? 64 * NV : 1];
+    __shared__ float sQphi[MLP ? NWAVE : 1][MLP ? 64 * NV : 1];
+    const int lim = SPEC == 1 ? HX_LIM_VANLEER : (SPEC == 2 ? HX_LIM_MLP : p.limiter);
     const int solver = SPEC ? HX_HLLC : p.riemann;
     double smax = 0.0;     // CFL rate of the cells this thread stores
 
@@ -173,7 +181,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     // images of this thread's x / y indices
     bool fx, fy;
     const int ii = bc_image(ic, n0, ng, p.bc[0][0], p.bc[0][1], fx);
-    const int jj = NDIM >= 2 ? bc_image(jc, n1, ng, p.bc[1][0], p.bc[1][1], fy) : 0;
+    // 1D: axis 1 indexes independent rows (a batch of 1D problems), one row per workgroup row
+    const int jj = NDIM >= 2 ? bc_image(jc, n1, ng, p.bc[1][0], p.bc[1][1], fy) : by;
     if (NDIM < 2)
         fy = false;
     const int gx = NDIM >= 1 ? ic + ng : 0;
@@ -213,12 +222,13 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     }
 
     // ------------------------------------------------------------------ plane loader
-    // The primitives of the (RX x RY) rectangle of a plane go to LDS.  Each thread loads its own
-    // cell (rectangle position (tx+1, ty+1)); the ring around the tile has fewer cells than the
-    // block has threads, so a thread loads at most one ring cell.  Loading is split in two halves:
-    // issue_plane() starts the global loads, commit_plane() converts and stores them, so the loads of
-    // plane k+1 are in flight while the x and y parts of the predictor of plane k run.
-    constexpr int NRING = NDIM >= 2 ? 2 * RX + 2 * BY : 2;
+    // The primitives of the (RX x RY) rectangle of a plane (predictor cells plus an S-wide ring)
+    // go to LDS.  Each thread loads its own cell (rectangle position (tx+S, ty+S)); the ring has
+    // fewer cells than the block has threads, so a thread loads at most one ring cell.  Loads are
+    // split into an issue half (global loads) and a commit half (flips, primitives, LDS stores), so
+    // the loads of the next planes are in flight while the x and y predictor of plane k runs.
+    // The own column runs S planes ahead of the LDS plane (the z stencil needs k-S .. k+S).
+    constexpr int NRING = NDIM >= 2 ? 2 * S * RX + 2 * S * BY : 2 * S;
     static_assert(NRING <= NT, "at most one ring cell per thread");
     const bool has_ring = tid < NRING;
     int ring_lds = 0, ri = 0, rj = 0;
@@ -226,29 +236,31 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     if (has_ring) {
         int lx, ly;
         if (NDIM >= 2) {
-            if (tid < RX) {
-                lx = tid;
-                ly = 0;
-            } else if (tid < 2 * RX) {
-                lx = tid - RX;
-                ly = RY - 1;
-            } else if (tid < 2 * RX + BY) {
-                lx = 0;
-                ly = tid - 2 * RX + 1;
+            if (tid < S * RX) {
+                lx = tid % RX;
+                ly = tid / RX;
+            } else if (tid < 2 * S * RX) {
+                const int r2 = tid - S * RX;
+                lx = r2 % RX;
+                ly = RY - S + r2 / RX;
             } else {
-                lx = RX - 1;
-                ly = tid - 2 * RX - BY + 1;
+                const int r3 = tid - 2 * S * RX;
+                const int side = r3 / (S * BY), r4 = r3 % (S * BY);
+                ly = S + r4 / S;
+                lx = (side == 0 ? 0 : RX - S) + r4 % S;
             }
         } else {
-            lx = tid == 0 ? 0 : RX - 1;
+            lx = tid < S ? tid : RX - 2 * S + tid;
             ly = 0;
         }
-        ri = bc_image(x0 - 2 + lx, n0, ng, p.bc[0][0], p.bc[0][1], rf0);
+        ri = bc_image(x0 - 1 - S + lx, n0, ng, p.bc[0][0], p.bc[0][1], rf0);
         if (NDIM >= 2)
-            rj = bc_image(y0 - 2 + ly, n1, ng, p.bc[1][0], p.bc[1][1], rf1);
+            rj = bc_image(y0 - 1 - S + ly, n1, ng, p.bc[1][0], p.bc[1][1], rf1);
+        else
+            rj = jj;
         ring_lds = ly * RX + lx;
     }
-    const int own = (NDIM >= 2 ? (ty + 1) * RX : 0) + tx + 1;
+    const int own = (NDIM >= 2 ? (ty + S) * RX : 0) + tx + S;
 
     auto raw_load = [&](int i0, int j0, int kk, R* q) {
         const long long off = ((long long)kk * n1 + j0) * n0 + i0;
@@ -260,46 +272,146 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
         fk = false;
         return NDIM == 3 ? bc_image(k, n2, ng, p.bc[2][0], p.bc[2][1], fk) : 0;
     };
-    auto issue_plane = [&](int k, R* qown, R* qring) {
+    auto issue_own = [&](int k, R* q) {
+        bool fk;
+        raw_load(ii, jj, plane_image(k, fk), q);
+    };
+    auto issue_ring = [&](int k, R* q) {
         bool fk;
         const int kk = plane_image(k, fk);
-        raw_load(ii, jj, kk, qown);
         if (has_ring)
-            raw_load(ri, rj, kk, qring);
+            raw_load(ri, rj, kk, q);
     };
-    auto commit_plane = [&](int k, int s, R* qown, R* wown, R* qring) {
+    // flips and primitives of the own cell of plane k (and the non-physical check)
+    auto commit_own = [&](int k, R* q, R* w) {
         bool fk;
         (void)plane_image(k, fk);
-        const bool kin = NDIM < 3 || (k >= 0 && k < n2);
         if (fx)
-            qown[1] = -qown[1];
+            q[1] = -q[1];
         if (fy)
-            qown[2] = -qown[2];
+            q[2] = -q[2];
         if (fk)
-            qown[3] = -qown[3];
-        to_prim<R, NV>(gas, qown, wown);
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            sW[s][v][own] = wown[v];
-        if (kin && interior && bad_state<R, NV>(qown, wown))
+            q[3] = -q[3];
+        to_prim<R, NV>(gas, q, w);
+        const bool kin = NDIM < 3 || (k >= 0 && k < n2);
+        if (kin && interior && bad_state<R, NV>(q, w))
             p.flag[0] = 1;
+    };
+    auto commit_ring = [&](int k, int s, R* q) {
+        bool fk;
+        (void)plane_image(k, fk);
         if (has_ring) {
             if (rf0)
-                qring[1] = -qring[1];
+                q[1] = -q[1];
             if (rf1)
-                qring[2] = -qring[2];
+                q[2] = -q[2];
             if (fk)
-                qring[3] = -qring[3];
+                q[3] = -q[3];
             R w[NV];
-            to_prim<R, NV>(gas, qring, w);
+            to_prim<R, NV>(gas, q, w);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 sW[s][v][ring_lds] = w[v];
         }
     };
+    auto store_own = [&](int s, const R* w) {
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            sW[s][v][own] = w[v];
+    };
+
+    // ------------------------------------------------------------------ learned limiter
+    MlpLane mlp;
+    if constexpr (MLP)
+        mlp_load(p.mlp, tid & 63, mlp);
+    // phi of the flagged stencils of every lane: the wave compacts them into its LDS queue and
+    // evaluates 16 per matrix-core tile; lanes without candidates take part in the tiles only
+    auto mlp_phase = [&](const bool* cand, float (*xn)[4], float* phi) {
+        const int lane = tid & 63, wv = tid >> 6;
+        int cnt = 0;
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            cnt += cand[v] ? 1 : 0;
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o)
+                incl += y;
+        }
+        const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+        int pos = incl - cnt;
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            if (cand[v]) {
+                const bf16x4_t b = pack_x(xn[v][0], xn[v][1], xn[v][2], xn[v][3]);
+                sQx[wv][pos] = __builtin_bit_cast(unsigned long long, b);
+                pos++;
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int t0 = 0; t0 < total; t0 += 16) {
+            const int e = t0 + (lane & 15);
+            bf16x4_t xb = {0, 0, 0, 0};
+            if (lane < 16 && e < total)
+                xb = __builtin_bit_cast(bf16x4_t, sQx[wv][e]);
+            const float ph = mlp_tile(mlp, xb);
+            if (lane < 16 && e < total)
+                sQphi[wv][e] = ph;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        pos = incl - cnt;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            phi[v] = 0.0f;
+            if (cand[v]) {
+                phi[v] = sQphi[wv][pos];
+                pos++;
+            }
+        }
+    };
+    // limited half increments of one axis from the stencil values w[-2..2] of every primitive
+    auto slopes = [&](R (*st)[NV], R cm, R cp, R* dl) {
+        if constexpr (!MLP) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                dl[v] = limit<R>(lim, cm * (st[2][v] - st[1][v]), cp * (st[3][v] - st[2][v]));
+        } else {
+            bool cand[NV];
+            float xn[NV][4], phi[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const float d[4] = {(float)(st[1][v] - st[0][v]), (float)(st[2][v] - st[1][v]),
+                                    (float)(st[3][v] - st[2][v]), (float)(st[4][v] - st[3][v])};
+                const float sm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
+                cand[v] = d[1] * d[2] > 0.0f;
+                const float is = cand[v] ? 1.0f / sm : 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    xn[v][q] = d[q] * is;
+            }
+            mlp_phase(cand, xn, phi);
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                R d = R(0);
+                if (cand[v]) {
+                    const R a = cm * (st[2][v] - st[1][v]);
+                    const R b = cp * (st[3][v] - st[2][v]);
+                    const R r = N::div(b, a);
+                    const R lm = fmin(R(2), R(2) * r);
+                    d = R(phi[v]) > lm ? N::div(R(2) * a * b, a + b) : R(phi[v]) * a;
+                }
+                dl[v] = d;
+            }
+        }
+    };
 
     // ------------------------------------------------------------------ persistent state
-    R qcur[NV], wcur[NV], qnext[NV], wnext[NV], wprev[NV];
+    // own column: wz[S + j] = primitives of plane k + j (j = -S..S), qz[j] = conserved of plane k + j
+    R wz[2 * S + 1][NV], qz[S + 1][NV];
     R acc[NV];     // plane k-1: U^n + x and y flux terms
     R fzlo[NV];    // z flux through the lower face of plane k-1
     R uzp[NV];     // +z half-step state of plane k-1
@@ -310,7 +422,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
         acc[v] = R(0);
         fzlo[v] = R(0);
         uzp[v] = R(0);
-        wprev[v] = R(0);
+#pragma unroll
+        for (int j = 0; j < 2 * S + 1; j++)
+            wz[j][v] = R(0);
     }
 #pragma unroll
     for (int v = 0; v < 5; v++)
@@ -323,30 +437,45 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
     if (NDIM == 3) {
         kbeg = k0 - 1;
         kend = k1;
-        // own column at k0-2 (z neighbour of the first predictor plane) and plane k0-1
-        bool fk;
-        const int kk = bc_image(k0 - 2, n2, ng, p.bc[2][0], p.bc[2][1], fk);
-        R q[NV], qr[NV];
-        fetch_cell<R, NV>(p, U, ii, jj, kk, fx, fy, fk, q);
-        to_prim<R, NV>(gas, q, wprev);
-        issue_plane(k0 - 1, qcur, qr);
-        commit_plane(k0 - 1, (k0 - 1) & 1, qcur, wcur, qr);
+        // own column, planes kbeg-S .. kbeg+S-1, and the LDS rectangle of plane kbeg
+#pragma unroll
+        for (int j = 0; j < 2 * S; j++) {
+            R q[NV];
+            issue_own(kbeg - S + j, q);
+            commit_own(kbeg - S + j, q, wz[j]);
+            if (j >= S) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    qz[j - S][v] = q[v];
+            }
+        }
+        R qr[NV];
+        issue_ring(kbeg, qr);
+        commit_ring(kbeg, kbeg & 1, qr);
+        store_own(kbeg & 1, wz[S]);
         // a valid state for the (unused) z flux below the first predictor plane
 #pragma unroll
         for (int v = 0; v < NV; v++)
-            uzp[v] = qcur[v];
+            uzp[v] = qz[0][v];
     } else {
         R qr[NV];
-        issue_plane(0, qcur, qr);
-        commit_plane(0, 0, qcur, wcur, qr);
+        issue_own(0, qz[0]);
+        issue_ring(0, qr);
+        commit_own(0, qz[0], wz[S]);
+        commit_ring(0, 0, qr);
+        store_own(0, wz[S]);
     }
     __syncthreads();
 
     for (int k = kbeg; k <= kend; ++k) {
         const int slot = NDIM == 3 ? (k & 1) : 0;
         R qring[NV];
-        if (NDIM == 3)
-            issue_plane(k + 1, qnext, qring);
+        if (NDIM == 3) {
+            issue_own(k + S, qz[S]);
+            issue_ring(k + 1, qring);
+        }
+        R(&wcur)[NV] = wz[S];
+        R(&qcur)[NV] = qz[0];
 
         // -------------------------------------------------------------- predictor, plane k
         bool fzk = false;
@@ -373,15 +502,21 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
         }
         {
             // x
+            R st[5][NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                st[0][v] = S == 2 ? sW[slot][v][own - 2] : R(0);
+                st[1][v] = sW[slot][v][own - 1];
+                st[2][v] = wcur[v];
+                st[3][v] = sW[slot][v][own + 1];
+                st[4][v] = S == 2 ? sW[slot][v][own + 2] : R(0);
+            }
+            slopes(st, cmx, cpx, dlt[0]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                R a = cmx * (wcur[v] - sW[slot][v][own - 1]);
-                R b = cpx * (sW[slot][v][own + 1] - wcur[v]);
-                R d = limit<R>(lim, a, b);
-                dlt[0][v] = d;
-                wm[v] = wcur[v] - d;
-                wp[v] = wcur[v] + d;
+                wm[v] = wcur[v] - dlt[0][v];
+                wp[v] = wcur[v] + dlt[0][v];
             }
             to_cons<R, NV>(gas, wm, um);
             to_cons<R, NV>(gas, wp, up);
@@ -392,15 +527,21 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
                 du[v] += lamx * (fm[v] - fp[v]);
         }
         if (NDIM >= 2) {
+            R st[5][NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                st[0][v] = S == 2 ? sW[slot][v][own - 2 * RX] : R(0);
+                st[1][v] = sW[slot][v][own - RX];
+                st[2][v] = wcur[v];
+                st[3][v] = sW[slot][v][own + RX];
+                st[4][v] = S == 2 ? sW[slot][v][own + 2 * RX] : R(0);
+            }
+            slopes(st, cmy, cpy, dlt[1]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                R a = cmy * (wcur[v] - sW[slot][v][own - RX]);
-                R b = cpy * (sW[slot][v][own + RX] - wcur[v]);
-                R d = limit<R>(lim, a, b);
-                dlt[1][v] = d;
-                wm[v] = wcur[v] - d;
-                wp[v] = wcur[v] + d;
+                wm[v] = wcur[v] - dlt[1][v];
+                wp[v] = wcur[v] + dlt[1][v];
             }
             to_cons<R, NV>(gas, wm, um);
             to_cons<R, NV>(gas, wp, up);
@@ -411,16 +552,24 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
                 du[v] += lamy * (fm[v] - fp[v]);
         }
         if (NDIM == 3) {
-            commit_plane(k + 1, (k + 1) & 1, qnext, wnext, qring);
+            commit_own(k + S, qz[S], wz[2 * S]);
+            commit_ring(k + 1, (k + 1) & 1, qring);
+            store_own((k + 1) & 1, wz[S + 1]);
+            R st[5][NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                st[0][v] = S == 2 ? wz[0][v] : R(0);
+                st[1][v] = wz[S - 1][v];
+                st[2][v] = wcur[v];
+                st[3][v] = wz[S + 1][v];
+                st[4][v] = S == 2 ? wz[2 * S][v] : R(0);
+            }
+            slopes(st, cmz, cpz, dlt[2]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                R a = cmz * (wcur[v] - wprev[v]);
-                R b = cpz * (wnext[v] - wcur[v]);
-                R d = limit<R>(lim, a, b);
-                dlt[2][v] = d;
-                wm[v] = wcur[v] - d;
-                wp[v] = wcur[v] + d;
+                wm[v] = wcur[v] - dlt[2][v];
+                wp[v] = wcur[v] + dlt[2][v];
             }
             to_cons<R, NV>(gas, wm, um);
             to_cons<R, NV>(gas, wp, up);
@@ -700,9 +849,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
             for (int v = 0; v < NV; v++) {
                 fzlo[v] = Fz[v];
                 uzp[v] = qpz[v];
-                wprev[v] = wcur[v];
-                wcur[v] = wnext[v];
-                qcur[v] = qnext[v];
+#pragma unroll
+                for (int j = 0; j < 2 * S; j++)
+                    wz[j][v] = wz[j + 1][v];
+#pragma unroll
+                for (int j = 0; j < S; j++)
+                    qz[j][v] = qz[j + 1][v];
             }
         }
     }

@@ -39,4 +39,16 @@ static hipError_t launch_sweep_t(const SweepParams& p, int ndim, int nvar, int g
     }
 }
 
+// learned-limiter form: FP32, 5..7 fields
+template <typename R>
+static hipError_t launch_sweep_mlp_t(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s)
+{
+    switch (nvar) {
+    case 5: return go_nv<R, 5, 2>(p, ndim, geom, s);
+    case 6: return go_nv<R, 6, 2>(p, ndim, geom, s);
+    case 7: return go_nv<R, 7, 2>(p, ndim, geom, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace hx

@@ -52,7 +52,8 @@ _lib = None
 # names of the exported entry points, as declared in include/hydro.h
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
            "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
-           "hx_set_zchunk", "hx_enclosed_mass", "hx_last_error", "hx_destroy"]
+           "hx_set_zchunk", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
+           "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_adam", "hx_last_error", "hx_destroy"]
 
 
 def load_library():
@@ -80,12 +81,18 @@ def load_library():
     L.hx_set_mlp.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
     L.hx_set_zchunk.argtypes = [vp, C.c_int]
     L.hx_enclosed_mass.argtypes = [vp, _DP]
+    L.hx_mlp_eval.argtypes = [vp, vp, C.c_longlong, vp, vp]
+    L.hx_mlp_features.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, vp]
+    L.hx_mlp_grad_workspace_bytes.argtypes = [C.c_longlong]
+    L.hx_mlp_grad_workspace_bytes.restype = C.c_size_t
+    L.hx_mlp_grad.argtypes = [vp, vp, vp, vp, vp, C.c_longlong, vp, vp, vp, C.c_size_t, vp]
+    L.hx_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.hx_last_error.argtypes = []
     L.hx_last_error.restype = C.c_char_p
     L.hx_destroy.argtypes = [vp]
     L.hx_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("hx_workspace_bytes", "hx_last_error", "hx_destroy"):
+        if name not in ("hx_workspace_bytes", "hx_last_error", "hx_destroy", "hx_mlp_grad_workspace_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -247,3 +254,80 @@ class Solver:
         out = np.zeros(int(_get(self.prob, "n")[0]))
         self._call(self.L.hx_enclosed_mass(self.ctx, out.ctypes.data_as(_DP)))
         return out
+
+
+# ----------------------------------------------------------------------------- learned limiter
+
+def _check(L, st):
+    if st != OK:
+        raise HydroError(st, L.hx_last_error().decode())
+
+
+def _stream_ptr(torch, stream):
+    return C.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def mlp_eval(w, x, stream=None):
+    """phi of the normalised stencils x [n, 4] (device FP32 tensors) with parameters w [1249]."""
+    import torch
+
+    L = load_library()
+    w = w.contiguous().float()
+    x = x.contiguous().float()
+    n = x.shape[0]
+    phi = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(L, L.hx_mlp_eval(C.c_void_p(w.data_ptr()), C.c_void_p(x.data_ptr()), C.c_longlong(n),
+                            C.c_void_p(phi.data_ptr()), _stream_ptr(torch, stream)))
+    return phi
+
+
+def mlp_features(fine, ratio: int, gamma: float, stream=None):
+    """Training samples (x [n,4], a, t, wt) from a device FP64 batch of 1D fine states [5, rows, nf]."""
+    import torch
+
+    L = load_library()
+    fine = fine.contiguous().double()
+    _, rows, nf = fine.shape
+    n = rows * (nf // ratio) * 5
+    dev = fine.device
+    x = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    a, t, wt = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+    _check(L, L.hx_mlp_features(C.c_void_p(fine.data_ptr()), rows, nf, ratio, float(gamma),
+                                C.c_void_p(x.data_ptr()), C.c_void_p(a.data_ptr()), C.c_void_p(t.data_ptr()),
+                                C.c_void_p(wt.data_ptr()), _stream_ptr(torch, stream)))
+    return x, a, t, wt
+
+
+class MlpTrainer:
+    """FP32 master weights, Adam moments and gradient scratch on the device."""
+
+    def __init__(self, w0, n_max: int, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.L = load_library()
+        self.w = torch.as_tensor(np.asarray(w0, dtype=np.float32)).to(device).contiguous()
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.grad = torch.zeros_like(self.w)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        nb = int(self.L.hx_mlp_grad_workspace_bytes(C.c_longlong(n_max)))
+        self.work = torch.empty(max(nb, 4), dtype=torch.uint8, device=device)
+        self.stream = stream
+        self.step_count = 0
+
+    def gradient(self, x, a, t, wt):
+        n = x.shape[0]
+        _check(self.L, self.L.hx_mlp_grad(
+            C.c_void_p(self.w.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(a.data_ptr()),
+            C.c_void_p(t.data_ptr()), C.c_void_p(wt.data_ptr()), C.c_longlong(n),
+            C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.loss.data_ptr()),
+            C.c_void_p(self.work.data_ptr()), C.c_size_t(self.work.numel()), _stream_ptr(self.torch, self.stream)))
+        return self.grad, self.loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        _check(self.L, self.L.hx_mlp_adam(
+            C.c_void_p(self.w.data_ptr()), C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.m.data_ptr()),
+            C.c_void_p(self.v.data_ptr()), self.step_count, float(lr), float(beta1), float(beta2), float(eps),
+            _stream_ptr(self.torch, self.stream)))

@@ -265,6 +265,48 @@ def riemann_states(rng: np.random.Generator, count: int, ncomp: int = 3):
     return rho, u, p
 
 
+def riemann_batch(nrows: int = 64, n: int = 1024, seed: int = 1000, cfl: float = 0.8,
+                  precision: str = "fp64", limiter: str = "vanleer", ng: int = GHOSTS_DEFAULT,
+                  mirror: bool = False) -> Problem:
+    """A batch of independent 1D Riemann problems on [0, 1] (interface at 0.5), one per row of a
+    Cartesian ndim-1 grid with n[1] = nrows: left/right states drawn from the learned-limiter
+    training distribution (rho log-U[0.1,10], p log-U[0.01,10], u U(-2,2)), gamma 1.4,
+    transmissive ends.  With mirror=True the second half of the rows are the mirror images
+    (x -> -x) of the first half."""
+    f = uniform_faces(0.0, 1.0, n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if mirror:
+        assert nrows % 2 == 0
+        h = nrows // 2
+        r0, u0, p0 = riemann_states(rng, 2 * h, ncomp=1)
+        # rows [0, h): (left, right) = (first, second) draw; rows [h, 2h): swapped, velocity negated
+        rho_s = np.concatenate([r0[:h], r0[h:], r0[h:], r0[:h]])
+        p_s = np.concatenate([p0[:h], p0[h:], p0[h:], p0[:h]])
+        u_s = np.concatenate([u0[:h], u0[h:], -u0[h:], -u0[:h]])
+        order = np.concatenate([np.arange(h), np.arange(2 * h, 3 * h), np.arange(h, 2 * h), np.arange(3 * h, 4 * h)])
+        rho_s, u_s, p_s = rho_s[order], u_s[order], p_s[order]
+    else:
+        rho_s, u_s, p_s = riemann_states(rng, 2 * nrows, ncomp=1)
+    left = (np.arange(n) < n // 2)[None, :]
+    rho = np.where(left, rho_s[:nrows, None], rho_s[nrows:, None])
+    u = np.where(left, u_s[:nrows, 0][:, None], u_s[nrows:, 0][:, None])
+    p = np.where(left, p_s[:nrows, None], p_s[nrows:, None])
+    z = np.zeros_like(rho)
+    U = _pack(rho, u, z, z, p, [], 1.4).reshape(5, 1, nrows, n)
+    bc = [["transmissive"] * 2, ["periodic"] * 2, ["periodic"] * 2]
+    smax = float(np.max(np.abs(u_s[:, 0]) + np.sqrt(1.4 * p_s / rho_s)))
+    return _mk("riemann_batch", 1, "cart", (n, nrows, 1), [f, _inactive("cart", 1), _inactive("cart", 2)], ng, bc,
+               U, nscalar=0, gamma=1.4, cfl=cfl, riemann="hllc", limiter=limiter, precision=precision,
+               meta={"smax": smax, "left": (rho_s[:nrows], u_s[:nrows, 0], p_s[:nrows]),
+                     "right": (rho_s[nrows:], u_s[nrows:, 0], p_s[nrows:])})
+
+
+def riemann_row(batch: Problem, row: int) -> Problem:
+    """One row of a batch as a stand-alone 1D problem (same grid and parameters)."""
+    return batch.with_(n=(batch.n[0], 1, 1), U0=np.ascontiguousarray(batch.U0[:, :, row:row + 1, :]),
+                       name=f"riemann_row{row}")
+
+
 def quadrant3d(n: int = 256, seed: int = 2000, octant: bool = False, precision: str = "fp32",
                limiter: str = "vanleer", ng: int = GHOSTS_MLP, nsteps: int = 0) -> Problem:
     """Learned-limiter evaluation problem: [0,1]^3, split at x, y (and z for octants) = 0.5,

@@ -478,3 +478,61 @@ def test_mlp_phi0_equals_first_order_scheme():
     a, _ = o_none.step(U, dt)
     b, _ = o_mlp.step(U, dt)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------- learned-limiter samples
+
+def _fine_batch(prims, nf):
+    """[5][nrows][nf] conserved state from per-row primitive profiles (rho, u, p) callables."""
+    xf = (np.arange(nf) + 0.5) / nf
+    U = np.zeros((5, len(prims), nf))
+    for r, (rho, u, p) in enumerate(prims):
+        R, V, Pp = rho(xf), u(xf), p(xf)
+        U[0, r] = R
+        U[1, r] = R * V
+        U[4, r] = Pp / 0.4 + 0.5 * R * V * V
+    return U
+
+
+def test_mlp_samples_linear_profiles():
+    """A linear fine profile of a conserved density restricts to a linear coarse profile: all four
+    differences equal (x = +-1), and the least-squares label slope equals the coarse difference
+    (t = a), so phi = 1 is the exact answer there."""
+    nf, R = 64, 4
+    U = _fine_batch([(lambda x: 1 + 0.5 * x, lambda x: 0 * x, lambda x: 1 + 0 * x),
+                     (lambda x: 2 - x, lambda x: 0 * x, lambda x: 0.5 + 0 * x)], nf)
+    x, a, t, wt = O.mlp_features(U, R, 1.4)
+    x = x.reshape(2, nf // R, 5, 4)
+    a, t, wt = (v.reshape(2, nf // R, 5) for v in (a, t, wt))
+    inner = slice(2, nf // R - 2)
+    assert np.all(wt[:, inner, 0] == 1) and np.all(wt[:, :2] == 0) and np.all(wt[:, -2:] == 0)
+    sign = np.array([1.0, -1.0])[:, None]
+    assert np.allclose(x[:, inner, 0], sign[:, :, None], rtol=1e-13)
+    assert np.allclose(a[:, inner, 0], sign, rtol=1e-13)
+    assert np.allclose(t[:, inner, 0], sign, rtol=1e-12)
+    # flat velocity and pressure: no sample
+    assert np.all(wt[:, :, 1:] == 0)
+
+
+def test_mlp_samples_piecewise_constant_fine_data_has_zero_label():
+    """Fine data constant inside every coarse cell (a staircase) has zero least-squares slope."""
+    nf, R = 64, 4
+    stairs = lambda x: 1.0 + np.floor(x * nf / R) * 0.1
+    U = _fine_batch([(stairs, lambda x: 0 * x, lambda x: 1 + 0 * x)], nf)
+    x, a, t, wt = O.mlp_features(U, R, 1.4)
+    live = wt > 0
+    assert live.sum() > 0
+    assert np.all(np.abs(t[live]) < 1e-12)
+    assert np.allclose(a[live], 1.0)
+
+
+def test_mlp_samples_skip_extrema():
+    """At a density maximum the two central differences change sign: no sample (TVD forces 0)."""
+    nf, R = 64, 4
+    U = _fine_batch([(lambda x: 1.0 + np.exp(-((x - 0.5) / 0.1) ** 2), lambda x: 0 * x, lambda x: 1 + 0 * x)], nf)
+    x, a, t, wt = O.mlp_features(U, R, 1.4)
+    wt = wt.reshape(nf // R, 5)[:, 0]
+    xx = x.reshape(nf // R, 5, 4)[:, 0]
+    peak = np.argmax(U[0, 0].reshape(-1, R).mean(axis=1))
+    assert wt[peak] == 0
+    assert np.all(np.abs(xx[wt > 0]) <= 1.0 + 1e-15)
