@@ -4,7 +4,10 @@ Workload: 3D Cartesian Sedov blast, 256^3 cells, 7 fields (5 conserved + 2 passi
 HLLC, van Leer, CFL 0.5 -- the plain FP64 path (the headline value) and the FP32 form, each a
 sequence of steps; one step = the CFL dt reduction + the fused sweep, with the time step kept on
 the device (no host synchronisation inside the timed loop).  Inputs are synthetic and resident in
-HBM before the timed region starts.
+HBM before the timed region starts.  The learned-limiter form runs on its own workload (2D Riemann
+quadrants in a 256^3 box, 5 fields) beside FP32 and FP64 van Leer on the same problem, reported under
+forms.learned with its L1 difference from the FP64 van Leer run and the share of stencils where the
+network is evaluated.
 
 Prints one JSON line (see the contract in the repository's documentation).  The roofline block
 refers to the dominant kernel, the fused sweep: algorithmic bytes per launch = 2 * nvar * b * cells
@@ -32,8 +35,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(hydro, torch, prob, form, steps, warmup, zchunk):
+def run_form(hydro, torch, prob, form, steps, warmup, zchunk, weights=None):
     s = hydro.Solver(prob, precision=form, zchunk=zchunk)
+    if weights is not None:
+        s.set_mlp(weights)
     s.set_state(prob.U0)
     stream = s.stream
     s.advance(warmup)
@@ -68,6 +73,61 @@ def run_form(hydro, torch, prob, form, steps, warmup, zchunk):
         "state": state,
     }
     s.close()
+    return out
+
+
+def monotone_fraction(torch, U, gamma):
+    """Share of (cell, axis, primitive) stencils with differences of one sign on both sides, i.e.
+    where the learned limiter evaluates its network (interior cells only)."""
+    rho = U[0]
+    inv = 1.0 / rho
+    u = U[1:4] * inv
+    p = (gamma - 1.0) * (U[4] - 0.5 * (U[1:4] * u).sum(dim=0))
+    W = torch.stack([rho, u[0], u[1], u[2], p])
+    tot, hit = 0, 0
+    for ax in (1, 2, 3):
+        d = torch.diff(W, dim=ax)
+        sl = [slice(None)] * 4
+        sl[ax] = slice(0, -1)
+        dm = d[tuple(sl)]
+        sl[ax] = slice(1, None)
+        dp = d[tuple(sl)]
+        hit += int((dm * dp > 0).sum().item())
+        tot += dm.numel()
+    return hit / tot
+
+
+def run_learned(hydro, torch, problems, steps, warmup, n, zchunk):
+    """Learned-limiter form on the quadrant Riemann workload, beside FP32 and FP64 van Leer."""
+    from paper_2503_04428_amd import learned
+
+    try:
+        w = learned.load_weights()
+    except (OSError, AssertionError) as e:
+        log(f"learned form skipped: no trained weights ({e})")
+        return None
+    base = problems.quadrant3d(n=n, seed=2000, octant=False, precision="fp32", limiter="mlp", ng=3)
+    cells = base.ncells
+    runs = {}
+    for name, lim, prec in [("learned_fp32", "mlp", "fp32"), ("vanleer_fp32", "vanleer", "fp32"),
+                            ("vanleer_fp64", "vanleer", "fp64")]:
+        pr = base.with_(limiter=lim, precision=prec)
+        r = run_form(hydro, torch, pr, prec, steps, warmup, zchunk, weights=w if lim == "mlp" else None)
+        log(f"{name}: {r['ms_per_step']:.3f} ms/step, sweep {r['sweep_ms_avg']:.3f} ms, "
+            f"{cells * steps / r['wall_s']:.3e} zone-cycles/s")
+        runs[name] = r
+    ref = runs["vanleer_fp64"]["state"]
+    out = {"workload": f"2D Riemann quadrants in a {n}^3 box (5 fields, transmissive, HLLC, CFL 0.5), seed 2000",
+           "steps": steps}
+    for name, r in runs.items():
+        b = 8 if name.endswith("fp64") else 4
+        diff = (r["state"] - ref).abs().reshape(5, -1).mean(dim=1) / ref.abs().reshape(5, -1).mean(dim=1)
+        out[name] = {"zone_cycles_per_s": cells * steps / r["wall_s"], "ms_per_step": r["ms_per_step"],
+                     "sweep_ms": r["sweep_ms_avg"],
+                     "sweep_hbm_gbs_algorithmic": 2 * 5 * b * cells / (r["sweep_ms_avg"] * 1e-3) / 1e9,
+                     "l1_rel_vs_vanleer_fp64_per_field": diff.cpu().numpy().tolist(),
+                     "speedup_vs_vanleer_fp64": runs["vanleer_fp64"]["wall_s"] / r["wall_s"]}
+    out["monotone_stencil_fraction"] = monotone_fraction(torch, runs["learned_fp32"]["state"][:, :, :, :], 1.4)
     return out
 
 
@@ -118,6 +178,9 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
+    ap.add_argument("--learned-steps", type=int, default=100,
+                    help="timed steps of the learned-limiter comparison (0: skip)")
+    ap.add_argument("--learned-n", type=int, default=256)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -151,6 +214,11 @@ def main():
             f"(min {r['sweep_ms_min']:.3f}), {cells * args.steps / r['wall_s']:.3e} zone-cycles/s")
         results[form] = r
 
+    learned_out = None
+    if args.learned_steps > 0:
+        learned_out = run_learned(hydro, torch, problems, args.learned_steps, args.warmup, args.learned_n,
+                                  args.zchunk)
+
     # accuracy of the FP32 form against the FP64 path (same initial state, same number of steps)
     l1 = None
     if "fp64" in results and "fp32" in results:
@@ -179,6 +247,8 @@ def main():
         }
     if l1 is not None:
         forms["fp32"]["l1_rel_vs_fp64_per_field"] = l1
+    if learned_out is not None:
+        forms["learned"] = learned_out
 
     if args.copy_ref_mib > 0:
         nb = args.copy_ref_mib * 1024 * 1024

@@ -42,29 +42,35 @@ UNITS = {
 
 def _compile(src: str, extra: list) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    # optional extra flags for tuning experiments (e.g. -DHX_MINW_FP64=2)
+    tune = os.environ.get("HX_EXTRA_FLAGS", "").split()
+    cmd = [HIPCC, *COMMON, *extra, *tune, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str | None = None) -> str:
+    global BUILD
+    if out is not None:
+        BUILD = os.path.join(os.path.dirname(os.path.abspath(out)), "_build_" + os.path.basename(out))
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(UNITS), int(os.environ.get("MAX_JOBS", "8")))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda kv: _compile(*kv), UNITS.items()))
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(LIB)
-    return LIB
+        print(lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, out=sys.argv[1] if len(sys.argv) > 1 else None)
     sys.exit(0)

@@ -20,6 +20,19 @@
 
 namespace hx {
 
+// Minimum waves per SIMD the register allocator must allow (launch-bound hint); overridable at
+// build time per precision.  More waves hide more latency but may force register spills.
+#ifndef HX_MINW_FP64
+#define HX_MINW_FP64 1
+#endif
+#ifndef HX_MINW_FP32
+#define HX_MINW_FP32 3
+#endif
+template <typename R>
+struct MinWaves {
+    static constexpr int value = sizeof(R) == 8 ? HX_MINW_FP64 : HX_MINW_FP32;
+};
+
 template <int NDIM>
 struct Tile;
 template <>
@@ -113,7 +126,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // limiter with HLLC (slope stencil of half-width 2, BF16 matrix-core network); SPEC = 0 reads the
 // limiter and the Riemann solver from the parameters.
 template <typename R, int NV, int NDIM, int GEOM, int SPEC>
-__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY)
+__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::value)
     sweep_kernel(const SweepParams p)
 {
     using N = Num<R>;

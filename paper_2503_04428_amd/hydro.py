@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhydro.so")
+# HX_LIB_PATH selects another build of the same library (tuning experiments)
+LIB_PATH = os.environ.get("HX_LIB_PATH") or os.path.join(HERE, "libhydro.so")
 
 OK, EINVAL, EHIP, ENONPHYS, ESTATE, ENOSPACE = 0, -1, -2, -3, -4, -5
 MLP_NPARAM = 1249
