@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the Sedov cube")
+    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod"],
+                    help="sedov (default, the headline line); rt, wedge, sod measure the other workloads")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
@@ -202,10 +204,24 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     hydro.load_library()
-    prob = problems.sedov3d(n=args.n)
+    if args.workload == "sedov":
+        prob = problems.sedov3d(n=args.n)
+        wl = f"sedov3d-{args.n}^3 (5 conserved + 2 passive scalars, HLLC, van Leer, CFL 0.5)"
+    elif args.workload == "rt":
+        prob = problems.rt3d()
+        wl = "rt3d-128x128x512 (uniform gravity, 1 scalar, periodic x/y, reflective z, HLLC, van Leer)"
+    elif args.workload == "wedge":
+        prob = problems.wedge3d()
+        wl = "wedge-1024x128x128 spherical (point + enclosed-mass gravity, 4 scalars, HLLC, van Leer)"
+    else:
+        prob = problems.sod(1024)
+        wl = "sod-1024 (1D, HLLC, van Leer, CFL 0.8)"
+    if args.workload != "sedov":
+        args.cpu_slab = 0
+        args.learned_steps = 0
     cells = prob.ncells
     nvar = prob.nvar
-    log(f"workload: sedov 3D {args.n}^3, nvar {nvar}, steps {args.steps}, warmup {args.warmup}")
+    log(f"workload: {wl}, nvar {nvar}, steps {args.steps}, warmup {args.warmup}")
 
     results = {}
     for form in [f.strip() for f in args.forms.split(",") if f.strip()]:
@@ -260,7 +276,7 @@ def main():
         log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
         del src, dst
 
-    traffic_bytes = recorded_traffic(head["form"]) if args.n == 256 else None
+    traffic_bytes = recorded_traffic(head["form"]) if (args.n == 256 and args.workload == "sedov") else None
     traffic = traffic_bytes / (head["sweep_ms_avg"] * 1e-3) / 1e9 if traffic_bytes else None
 
     cpu = None
@@ -282,7 +298,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head["form"] == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"sedov3d-{args.n}^3 (5 conserved + 2 passive scalars, HLLC, van Leer, CFL 0.5)",
+        "config": {"workload": wl,
                    "cells": cells, "nvar": nvar, "form": head["form"], "dt": "CFL, on device every step"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

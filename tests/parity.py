@@ -10,17 +10,23 @@ def announce(msg: str):
     sys.stdout.flush()
 
 
-def parity_tolerance(Uo: np.ndarray, rel: float = 1e-12, absf: float = 1e-14) -> np.ndarray:
-    """Per cell |dU| <= rel |U_oracle| + absf max_cells |U_oracle| of that field."""
+def parity_tolerance(Uo: np.ndarray, rel: float = 1e-12, absf: float = 1e-14, flow_scale: bool = False) -> np.ndarray:
+    """Per cell |dU| <= rel |U_oracle| + absf * scale of that field, scale = max_cells |U_oracle|.
+    With flow_scale, the three momenta share one scale, at least sqrt(max rho * max E) (the momentum
+    of the flow's energy), so that a momentum that is ~0 everywhere is not judged on its own size."""
     nv = Uo.shape[0]
     scale = np.abs(Uo).reshape(nv, -1).max(axis=1)
+    if flow_scale:
+        ms = max(scale[1:4].max(), np.sqrt(scale[0] * scale[4]))
+        scale[1:4] = ms
     return rel * np.abs(Uo) + absf * scale.reshape((nv,) + (1,) * (Uo.ndim - 1))
 
 
-def assert_parity(Ug: np.ndarray, Uo: np.ndarray, rel: float = 1e-12, absf: float = 1e-14, what: str = ""):
+def assert_parity(Ug: np.ndarray, Uo: np.ndarray, rel: float = 1e-12, absf: float = 1e-14, what: str = "",
+                  flow_scale: bool = False):
     assert Ug.shape == Uo.shape, (Ug.shape, Uo.shape)
     assert np.all(np.isfinite(Ug)), f"{what}: non-finite GPU values"
-    tol = parity_tolerance(Uo, rel, absf)
+    tol = parity_tolerance(Uo, rel, absf, flow_scale)
     err = np.abs(Ug - Uo)
     bad = err > tol
     if bad.any():

@@ -209,3 +209,124 @@ def test_zchunk_does_not_change_results(H):
         s.close()
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+# ---------------------------------------------------------------------------- full-size workloads
+
+def _sampled_first_step(H, prob, precision, boxes, rel, absf, weights=None, oracle_weights=None, flow_scale=False):
+    o = O.Oracle(prob, mlp_weights=oracle_weights)
+    U0 = prob.U0
+    dt, st = o.compute_dt(U0)
+    assert st == 0
+    s = H.Solver(prob, precision=precision)
+    if weights is not None:
+        s.set_mlp(weights)
+    s.set_state(U0)
+    s.step(dt)
+    Ug = s.state_numpy()
+    s.close()
+    worst = 0.0
+    for lo, hi in boxes:
+        ob, st = o.step_box(U0, dt, lo, hi)
+        gb = Ug[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        assert_parity(gb, ob, rel=rel, absf=absf, what=f"{prob.name} {precision} box {lo}-{hi}",
+                      flow_scale=flow_scale)
+        worst = max(worst, max_rel(gb, ob))
+    return worst
+
+
+def _boxes(n, centre, rng, k=5, size=4):
+    out = [(tuple(max(0, c - 3) for c in centre), tuple(min(n[d], centre[d] + 3) for d in range(3))),
+           ((0, 0, 0), (min(3, n[0]), min(3, n[1]), min(3, n[2]))),
+           (tuple(n[d] - min(3, n[d]) for d in range(3)), tuple(n))]
+    for _ in range(k):
+        lo = [int(rng.integers(0, n[d] - size + 1)) for d in range(3)]
+        out.append((tuple(lo), tuple(lo[d] + size for d in range(3))))
+    return out
+
+
+# FP32-form tolerance, from its arithmetic: FP32 rounding (6e-8) through one step of ~10^3 operations
+# per cell, relative to the value, plus a floor for fields that cancel; momenta are floored on the
+# flow's momentum scale (a component that is ~0 everywhere has no scale of its own)
+FP32_REL, FP32_ABS = 2e-5, 2e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_rt_sampled(H, precision):
+    prob = P.rt3d()
+    announce(f"full-size RT 128x128x512 {precision} first step")
+    rng = np.random.default_rng(1)
+    rel, absf = (1e-12, 1e-14) if precision == "fp64" else (FP32_REL, FP32_ABS)
+    w = _sampled_first_step(H, prob, precision, _boxes(prob.n, (64, 64, 256), rng) +
+                            [((60, 60, 0), (68, 68, 3)), ((0, 60, 508), (4, 68, 512))], rel, absf,
+                            flow_scale=precision == "fp32")
+    print(f"RT {precision}: max relative difference on samples {w:.3e}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_wedge_sampled(H, precision):
+    prob = P.wedge3d()
+    announce(f"full-size wedge 1024x128x128 {precision} first step")
+    rng = np.random.default_rng(2)
+    rel, absf = (1e-12, 1e-14) if precision == "fp64" else (FP32_REL, FP32_ABS)
+    w = _sampled_first_step(H, prob, precision, _boxes(prob.n, (18, 64, 64), rng) +
+                            [((0, 0, 60), (4, 4, 64)), ((1020, 124, 124), (1024, 128, 128))], rel, absf,
+                            flow_scale=precision == "fp32")
+    print(f"wedge {precision}: max relative difference on samples {w:.3e}")
+
+
+def test_full_size_learned_sampled(H):
+    """Learned form at 256^3 with the trained network: BF16 inference vs the FP64 oracle network
+    (BF16-rounded parameters) on sampled boxes around the quadrant interfaces."""
+    from paper_2503_04428_amd import learned
+    try:
+        w = learned.load_weights()
+    except OSError:
+        pytest.skip("no trained weights")
+    prob = P.quadrant3d(n=256, limiter="mlp", precision="fp32")
+    announce("full-size learned 256^3 first step")
+    rng = np.random.default_rng(3)
+    boxes = [((124, 124, 0), (132, 132, 4)), ((125, 30, 100), (131, 36, 104)), ((30, 125, 7), (36, 131, 11))]
+    boxes += _boxes(prob.n, (128, 128, 128), rng, k=3)
+    # BF16 inference perturbs phi by ~1e-3, which moves the slopes of monotone stencils by that
+    # relative amount; one step carries ~dt/dx of it into the state
+    _sampled_first_step(H, prob, "fp32", boxes, 2e-3, 2e-4, weights=w, oracle_weights=O.bf16_round(w),
+                        flow_scale=True)
+
+
+# ---------------------------------------------------------------------------- FP32 form accuracy
+
+def test_fp32_form_accuracy_sod_and_sedov(H):
+    """FP32 form: L1 error against the FP64 oracle and against the exact Sod solution (reported;
+    the FP32 error must be far below the discretisation error)."""
+    from oracle import exact
+    announce("fp32 form accuracy")
+    pr = P.sod(1024)
+    o = O.Oracle(pr)
+    Uo, t, steps, dts = o.run(pr.U0.copy(), t_end=0.2)
+    s = H.Solver(pr, precision="fp32")
+    s.set_state(pr.U0)
+    for dt in dts:
+        s.step(dt)
+    Ug = s.state_numpy()
+    f = pr.faces[0][pr.ng:pr.ng + 1025]
+    r, u, p = exact.cell_average(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, f, 0.5, 0.2, sub=16)
+    e_fp32_oracle = np.abs(Ug[0, 0, 0] - Uo[0, 0, 0]).mean()
+    e_oracle_exact = np.abs(Uo[0, 0, 0] - r).mean()
+    e_fp32_exact = np.abs(Ug[0, 0, 0] - r).mean()
+    print(f"Sod 1024 rho L1: fp32-vs-oracle {e_fp32_oracle:.3e}, oracle-vs-exact {e_oracle_exact:.3e}, "
+          f"fp32-vs-exact {e_fp32_exact:.3e}")
+    assert e_fp32_oracle < 1e-2 * e_oracle_exact
+    assert abs(e_fp32_exact - e_oracle_exact) < 1e-2 * e_oracle_exact
+    # Sedov: FP32 vs FP64 oracle after 100 steps at 32^3
+    pr = P.sedov3d(n=32)
+    o = O.Oracle(pr)
+    Uo, t, steps, dts = o.run(pr.U0.copy(), nsteps=100)
+    s = H.Solver(pr, precision="fp32")
+    s.set_state(pr.U0)
+    for dt in dts:
+        s.step(dt)
+    Ug = s.state_numpy()
+    rel = np.abs(Ug - Uo).reshape(7, -1).mean(axis=1) / np.maximum(np.abs(Uo).reshape(7, -1).mean(axis=1), 1e-300)
+    print("Sedov 32^3 100 steps, fp32 form L1 relative error per field:", rel)
+    assert np.all(rel[[0, 4, 5, 6]] < 1e-4)
