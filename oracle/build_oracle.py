@@ -19,6 +19,18 @@ def build(openmp: bool = False) -> str:
     return LIB
 
 
+def build_opcount() -> str:
+    """The oracle compiled as C++ with a counting FP64 type (opcount.cpp): same entry points plus
+    or_opcount / or_opcount_reset, same arithmetic."""
+    lib = os.path.join(HERE, "liboracle_opcount.so")
+    src = os.path.join(HERE, "opcount.cpp")
+    flags = [f for f in CFLAGS if not f.startswith("-std=")]
+    cmd = ["g++", *flags, "-std=gnu++17", "-I", HERE, "-o", lib + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
 if __name__ == "__main__":
     print(build())
     sys.exit(0)

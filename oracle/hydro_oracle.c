@@ -26,6 +26,12 @@
 
 #define MAXV 16
 
+/* Marks work that repeats an evaluation made elsewhere in the step; a no-op here.  The
+ * op-counting build (opcount.cpp) books the operations inside it apart. */
+#ifndef OR_REPEATED_WORK
+#define OR_REPEATED_WORK(on)
+#endif
+
 typedef struct {
     const or_config *c;
     int nvar;
@@ -785,7 +791,10 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                         L[v] = FS[((d * 2 + 1) * nv + v) * np + ip];
                         R[v] = FS[((d * 2 + 0) * nv + v) * np + ipq];
                     }
+                    /* the upper face's flux is the next cell's lower-face flux once more */
+                    OR_REPEATED_WORK(1);
                     riemann(c->riemann, d, nv, c->gamma, x.gm1, L, R, Fp[d]);
+                    OR_REPEATED_WORK(0);
                     if (c->geom == OR_CART) {
                         double mu = dt / dxc(c, d, cidx[d]);
                         for (int v = 0; v < nv; v++)

@@ -13,6 +13,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+OPCOUNT_LIB_PATH = os.path.join(HERE, "liboracle_opcount.so")
 
 GEOM = {"cart": 0, "sph": 1}
 RIEMANN = {"hll": 0, "hllc": 1}
@@ -35,16 +36,20 @@ class OrConfig(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(path: str = LIB_PATH):
+    """The oracle's C library (or a library with the same entry points, e.g. the op-counting
+    build), loaded once per path."""
+    if path not in _libs:
+        if not os.path.exists(path):
             from . import build_oracle
-            build_oracle.build()
-        L = C.CDLL(LIB_PATH)
+            if path == LIB_PATH:
+                build_oracle.build()
+            elif path == OPCOUNT_LIB_PATH:
+                build_oracle.build_opcount()
+        L = C.CDLL(path)
         cp = C.POINTER(OrConfig)
         L.or_step.argtypes = [cp, _DP, C.c_double, _DP]
         L.or_step_box.argtypes = [cp, _DP, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), _DP]
@@ -64,8 +69,13 @@ def lib():
         L.or_mlp_loss_grad.restype = C.c_double
         L.or_mlp_features.argtypes = [_DP, C.c_int, C.c_int, C.c_int, C.c_double, _DP, _DP, _DP, _DP]
         L.or_mlp_features.restype = None
-        _lib = L
-    return _lib
+        if hasattr(L, "or_opcount"):
+            L.or_opcount.argtypes = [C.POINTER(C.c_ulonglong)]
+            L.or_opcount.restype = None
+            L.or_opcount_reset.argtypes = []
+            L.or_opcount_reset.restype = None
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a: np.ndarray):
@@ -80,8 +90,9 @@ def _get(p, k):
 class Oracle:
     """FP64 oracle bound to one problem description."""
 
-    def __init__(self, prob, mlp_weights: np.ndarray | None = None):
+    def __init__(self, prob, mlp_weights: np.ndarray | None = None, library: str = LIB_PATH):
         self.prob = prob
+        self._L = lib(library)
         self.ndim = int(_get(prob, "ndim"))
         self.n = tuple(int(v) for v in _get(prob, "n"))
         self.nscalar = int(_get(prob, "nscalar"))
@@ -129,7 +140,7 @@ class Oracle:
     def step(self, U: np.ndarray, dt: float) -> tuple[np.ndarray, int]:
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
         out = np.empty_like(U)
-        st = lib().or_step(self._cfgp(), _ptr(U), float(dt), _ptr(out))
+        st = self._L.or_step(self._cfgp(), _ptr(U), float(dt), _ptr(out))
         if st == EINVAL:
             raise ValueError("oracle: invalid configuration")
         if st == ENOMEM:
@@ -142,7 +153,7 @@ class Oracle:
         hi3 = (C.c_int * 3)(*[int(v) for v in hi])
         ext = [int(hi[d]) - int(lo[d]) for d in range(3)]
         out = np.empty((self.nvar, ext[2], ext[1], ext[0]))
-        st = lib().or_step_box(self._cfgp(), _ptr(U), float(dt), lo3, hi3, _ptr(out))
+        st = self._L.or_step_box(self._cfgp(), _ptr(U), float(dt), lo3, hi3, _ptr(out))
         if st == EINVAL:
             raise ValueError("oracle: invalid box or configuration")
         return out, st
@@ -150,7 +161,7 @@ class Oracle:
     def compute_dt(self, U: np.ndarray) -> tuple[float, int]:
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
         dt = C.c_double(0.0)
-        st = lib().or_compute_dt(self._cfgp(), _ptr(U), C.byref(dt))
+        st = self._L.or_compute_dt(self._cfgp(), _ptr(U), C.byref(dt))
         if st == EINVAL:
             raise ValueError("oracle: invalid configuration")
         return dt.value, st
@@ -158,13 +169,13 @@ class Oracle:
     def totals(self, U: np.ndarray) -> np.ndarray:
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
         out = np.zeros(self.nvar)
-        lib().or_totals(self._cfgp(), _ptr(U), _ptr(out))
+        self._L.or_totals(self._cfgp(), _ptr(U), _ptr(out))
         return out
 
     def enclosed_mass(self, U: np.ndarray) -> np.ndarray:
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
         out = np.zeros(self.n[0])
-        st = lib().or_enclosed_mass(self._cfgp(), _ptr(U), _ptr(out))
+        st = self._L.or_enclosed_mass(self._cfgp(), _ptr(U), _ptr(out))
         if st:
             raise ValueError("oracle: enclosed mass needs a spherical grid")
         return out
@@ -250,3 +261,28 @@ def bf16_round(w) -> np.ndarray:
     f = np.ascontiguousarray(w, dtype=np.float32).view(np.uint32).astype(np.uint64)
     f = (f + 0x7FFF + ((f >> 16) & 1)) & 0xFFFF0000
     return f.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+OPCOUNT_FIELDS = ("add", "mul", "div", "sqrt", "cmp", "minmax_abs", "transc")
+
+
+def opcount_step(prob, U: np.ndarray, dt: float) -> dict:
+    """Operations of the oracle's step on state U (op-counting build of the same C source): a dict
+    of counts per category of the algorithm's work, plus 'flops' = add + mul + div + sqrt, and
+    'repeated' with the same counts for the work the oracle repeats (the second evaluation of
+    every face flux), which is not part of the algorithm's work."""
+    o = Oracle(prob, library=OPCOUNT_LIB_PATH)
+    L = o._L
+    L.or_opcount_reset()
+    out, st = o.step(U, dt)
+    c = (C.c_ulonglong * 14)()
+    L.or_opcount(c)
+    res = {k: int(v) for k, v in zip(OPCOUNT_FIELDS, c[:7])}
+    res["flops"] = res["add"] + res["mul"] + res["div"] + res["sqrt"]
+    rep = {k: int(v) for k, v in zip(OPCOUNT_FIELDS, c[7:])}
+    rep["flops"] = rep["add"] + rep["mul"] + rep["div"] + rep["sqrt"]
+    res["repeated"] = rep
+    res["state"] = out
+    res["status"] = st
+    return res
+
