@@ -148,8 +148,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
     __shared__ R sGy[NV][NYB];            // y flux through the lower face of every cell
     __shared__ double sRed[NWAVE];
     // learned limiter: per-wave queue of the stencils that need the network, and its outputs
-    __shared__ unsigned long long sQx[MLP ? NWAVE : 1][MLP ? 64 * NV : 1];
-    __shared__ float sQphi[MLP ? NWAVE : 1][MLP ? 64 * NV : 1];
+    __shared__ unsigned long long sQ[MLP ? NWAVE : 1][MLP ? 2 * 64 * NV : 1];
+    __shared__ __align__(16) unsigned char sMlpRaw[MLP ? sizeof(MlpShared) : 16];  // network operands
+    MlpShared& sMlp = *reinterpret_cast<MlpShared*>(sMlpRaw);
     const int lim = SPEC == 1 ? HX_LIM_VANLEER : (SPEC == 2 ? HX_LIM_MLP : p.limiter);
     const int solver = SPEC ? HX_HLLC : p.riemann;
     double smax = 0.0;     // CFL rate of the cells this thread stores
@@ -334,92 +335,102 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
     };
 
     // ------------------------------------------------------------------ learned limiter
-    MlpLane mlp;
+    // The network's operands live once per block in LDS (a barrier follows before the first use).
+    // slopes_mlp() handles na axes at once (x and y together, z alone): each monotone (lane, axis,
+    // variable) stencil gets a slot of the wave's LDS queue (ordered by axis, variable, lane), the
+    // wave evaluates 16 queued stencils per matrix-core tile and writes phi over the low word of
+    // the stencil's slot.  A wave without candidates skips all of it.
     if constexpr (MLP)
-        mlp_load(p.mlp, tid & 63, mlp);
-    // phi of the flagged stencils of every lane: the wave compacts them into its LDS queue and
-    // evaluates 16 per matrix-core tile; lanes without candidates take part in the tiles only
-    auto mlp_phase = [&](const bool* cand, float (*xn)[4], float* phi) {
-        const int lane = tid & 63, wv = tid >> 6;
-        int cnt = 0;
+        mlp_fill_shared(p.mlp, tid, NT, sMlp);
+    // limited half increments of one axis; st(j, v) = primitive v at offset j - 2 along the axis
+    auto slopes = [&](auto&& st, R cm, R cp, R* dl) {
 #pragma unroll
         for (int v = 0; v < NV; v++)
-            cnt += cand[v] ? 1 : 0;
-        int incl = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o, 64);
-            if (lane >= o)
-                incl += y;
-        }
-        const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
-        int pos = incl - cnt;
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            if (cand[v]) {
-                const bf16x4_t b = pack_x(xn[v][0], xn[v][1], xn[v][2], xn[v][3]);
-                sQx[wv][pos] = __builtin_bit_cast(unsigned long long, b);
-                pos++;
-            }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int t0 = 0; t0 < total; t0 += 16) {
-            const int e = t0 + (lane & 15);
-            bf16x4_t xb = {0, 0, 0, 0};
-            if (lane < 16 && e < total)
-                xb = __builtin_bit_cast(bf16x4_t, sQx[wv][e]);
-            const float ph = mlp_tile(mlp, xb);
-            if (lane < 16 && e < total)
-                sQphi[wv][e] = ph;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        pos = incl - cnt;
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            phi[v] = 0.0f;
-            if (cand[v]) {
-                phi[v] = sQphi[wv][pos];
-                pos++;
-            }
-        }
+            dl[v] = limit<R>(lim, cm * (st(2, v) - st(1, v)), cp * (st(3, v) - st(2, v)));
     };
-    // limited half increments of one axis from the stencil values w[-2..2] of every primitive
-    auto slopes = [&](R (*st)[NV], R cm, R cp, R* dl) {
-        if constexpr (!MLP) {
+    // learned form of slopes() for the axes a0 .. a0+na-1 (na <= 2); st(a, j, v) = primitive v at
+    // offset j - 2 along axis a.  The stencils are read again after the queue fence, so that they
+    // are not held in registers across the network tiles.
+    auto slopes_mlp = [&](auto&& st, int a0, int na, const R* cmv, const R* cpv, R (*dl)[NV]) {
+        const int lane = tid & 63, wv = tid >> 6;
+        float d[2][NV][4];  // stencil differences
+        unsigned long long bal[2][NV];  // candidates: monotone stencils, d1 d2 > 0
+        unsigned total = 0;
+#pragma unroll
+        for (int a = 0; a < na; a++)
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    d[a][v][j] = st(a0 + a, j + 1, v) - st(a0 + a, j, v);
+                bal[a][v] = __builtin_amdgcn_ballot_w64(d[a][v][1] * d[a][v][2] > 0.0f);
+                total += (unsigned)__builtin_popcountll(bal[a][v]);
+                dl[a][v] = R(0);
+            }
+        if (total == 0)
+            return;
+        auto cand = [&](int a, int v) { return ((bal[a][v] >> lane) & 1ull) != 0; };
+        auto slot = [&](int a, int v) {
+            unsigned base = 0;
+#pragma unroll
+            for (int b = 0; b <= a; b++)
+#pragma unroll
+                for (int u = 0; u < NV; u++)
+                    if (b < a || u < v)
+                        base += (unsigned)__builtin_popcountll(bal[b][u]);
+            return (int)(base + __builtin_amdgcn_mbcnt_hi((unsigned)(bal[a][v] >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)bal[a][v], 0u)));
+        };
+        // queue d / max|d| of every candidate as BF16 (stencils without candidates skip, uniformly)
+#pragma unroll
+        for (int a = 0; a < na; a++)
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                dl[v] = limit<R>(lim, cm * (st[2][v] - st[1][v]), cp * (st[3][v] - st[2][v]));
-        } else {
-            bool cand[NV];
-            float xn[NV][4], phi[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                const float d[4] = {(float)(st[1][v] - st[0][v]), (float)(st[2][v] - st[1][v]),
-                                    (float)(st[3][v] - st[2][v]), (float)(st[4][v] - st[3][v])};
-                const float sm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
-                cand[v] = d[1] * d[2] > 0.0f;
-                const float is = cand[v] ? 1.0f / sm : 0.0f;
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    xn[v][q] = d[q] * is;
-            }
-            mlp_phase(cand, xn, phi);
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                R d = R(0);
-                if (cand[v]) {
-                    const R a = cm * (st[2][v] - st[1][v]);
-                    const R b = cp * (st[3][v] - st[2][v]);
-                    const R r = N::div(b, a);
-                    const R lm = fmin(R(2), R(2) * r);
-                    d = R(phi[v]) > lm ? N::div(R(2) * a * b, a + b) : R(phi[v]) * a;
+                if (bal[a][v]) {
+                    const float* dd = d[a][v];
+                    const float is = __builtin_amdgcn_rcpf(
+                        fmaxf(fmaxf(fabsf(dd[0]), fabsf(dd[1])), fmaxf(fabsf(dd[2]), fabsf(dd[3]))));
+                    const unsigned long long x = __builtin_bit_cast(
+                        unsigned long long, pack_x(dd[0] * is, dd[1] * is, dd[2] * is, dd[3] * is));
+                    if (cand(a, v))
+                        sQ[wv][slot(a, v)] = x;
                 }
-                dl[v] = d;
-            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float* qphi = reinterpret_cast<float*>(sQ[wv]);  // phi of slot e at qphi[2 e]
+        for (unsigned t0 = 0; t0 < total; t0 += 16) {
+            const unsigned e = t0 + (lane & 15);
+            // lanes past the queue's end evaluate a copy of its last entry, which is not stored
+            const bf16x4_t xb = __builtin_bit_cast(bf16x4_t, sQ[wv][e < total ? e : total - 1]);
+            MlpLane m;
+            mlp_lane_from_shared(sMlp, lane, m);
+            const float ph = mlp_tile(m, xb);
+            if (lane < 16 && e < total)
+                qphi[2 * e] = ph;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // phi a inside the TVD region phi <= min(2, 2 b/a), van Leer's slope outside it
+        // (a b > 0 here, so phi > 2 b/a is phi |a| > 2 |b|)
+        R phv[2][NV];
+#pragma unroll
+        for (int a = 0; a < na; a++)
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                phv[a][v] = qphi[2 * (cand(a, v) ? slot(a, v) : 0)];
+#pragma unroll
+        for (int a = 0; a < na; a++)
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const R phi = phv[a][v];
+                const R da = cmv[a] * (st(a0 + a, 2, v) - st(a0 + a, 1, v));
+                const R db = cpv[a] * (st(a0 + a, 3, v) - st(a0 + a, 2, v));
+                const bool tvd = !(phi > R(2) || phi * fabs(da) > R(2) * fabs(db));
+                const R s = tvd ? phi * da : R(2) * da * db * R(__builtin_amdgcn_rcpf((float)(da + db)));
+                dl[a][v] = cand(a, v) ? s : R(0);
+            }
     };
 
     // ------------------------------------------------------------------ persistent state
@@ -506,6 +517,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
             if (fzk && p.gravity == HX_GRAV_UNIFORM)
                 g[2] = -g[2];
         }
+        // primitive v at offset j - 2 along axis a from the plane in LDS (x, y) or the own column (z)
+        auto stv = [&](int a, int j, int v) -> R {
+            if (a == 2)
+                return wz[S + j - 2][v];
+            return j == 2 ? wcur[v] : sW[slot][v][own + (j - 2) * (a == 0 ? 1 : RX)];
+        };
         R dlt[3][NV];  // half increments of the limited slopes
         R du[NV];
 #pragma unroll
@@ -515,16 +532,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
         }
         {
             // x
-            R st[5][NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                st[0][v] = S == 2 ? sW[slot][v][own - 2] : R(0);
-                st[1][v] = sW[slot][v][own - 1];
-                st[2][v] = wcur[v];
-                st[3][v] = sW[slot][v][own + 1];
-                st[4][v] = S == 2 ? sW[slot][v][own + 2] : R(0);
+            if constexpr (MLP) {
+                const R cmv[2] = {cmx, cmy}, cpv[2] = {cpx, cpy};
+                slopes_mlp(stv, 0, NDIM >= 2 ? 2 : 1, cmv, cpv, dlt);
+            } else {
+                slopes([&](int j, int v) { return stv(0, j, v); }, cmx, cpx, dlt[0]);
             }
-            slopes(st, cmx, cpx, dlt[0]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
@@ -540,16 +553,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
                 du[v] += lamx * (fm[v] - fp[v]);
         }
         if (NDIM >= 2) {
-            R st[5][NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                st[0][v] = S == 2 ? sW[slot][v][own - 2 * RX] : R(0);
-                st[1][v] = sW[slot][v][own - RX];
-                st[2][v] = wcur[v];
-                st[3][v] = sW[slot][v][own + RX];
-                st[4][v] = S == 2 ? sW[slot][v][own + 2 * RX] : R(0);
-            }
-            slopes(st, cmy, cpy, dlt[1]);
+            if constexpr (!MLP)
+                slopes([&](int j, int v) { return stv(1, j, v); }, cmy, cpy, dlt[1]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
@@ -568,16 +573,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
             commit_own(k + S, qz[S], wz[2 * S]);
             commit_ring(k + 1, (k + 1) & 1, qring);
             store_own((k + 1) & 1, wz[S + 1]);
-            R st[5][NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                st[0][v] = S == 2 ? wz[0][v] : R(0);
-                st[1][v] = wz[S - 1][v];
-                st[2][v] = wcur[v];
-                st[3][v] = wz[S + 1][v];
-                st[4][v] = S == 2 ? wz[2 * S][v] : R(0);
-            }
-            slopes(st, cmz, cpz, dlt[2]);
+            if constexpr (MLP)
+                slopes_mlp(stv, 2, 1, &cmz, &cpz, dlt + 2);
+            else
+                slopes([&](int j, int v) { return stv(2, j, v); }, cmz, cpz, dlt[2]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
