@@ -29,6 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector peaks: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz (FP64), twice that with
+# packed FP32
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -70,6 +74,7 @@ def run_form(hydro, torch, prob, form, steps, warmup, zchunk, weights=None):
         "ms_per_step": wall * 1e3 / steps,
         "sweep_ms_avg": sum(sweep_ms) / len(sweep_ms),
         "sweep_ms_min": min(sweep_ms),
+        "zchunk": s.zchunk(),
         "state": state,
     }
     s.close()
@@ -114,7 +119,7 @@ def run_learned(hydro, torch, problems, steps, warmup, n, zchunk):
         pr = base.with_(limiter=lim, precision=prec)
         r = run_form(hydro, torch, pr, prec, steps, warmup, zchunk, weights=w if lim == "mlp" else None)
         log(f"{name}: {r['ms_per_step']:.3f} ms/step, sweep {r['sweep_ms_avg']:.3f} ms, "
-            f"{cells * steps / r['wall_s']:.3e} zone-cycles/s")
+            f"{cells * steps / r['wall_s']:.3e} zone-cycles/s, kz {r['zchunk']}")
         runs[name] = r
     ref = runs["vanleer_fp64"]["state"]
     out = {"workload": f"2D Riemann quadrants in a {n}^3 box (5 fields, transmissive, HLLC, CFL 0.5), seed 2000",
@@ -125,6 +130,7 @@ def run_learned(hydro, torch, problems, steps, warmup, n, zchunk):
         out[name] = {"zone_cycles_per_s": cells * steps / r["wall_s"], "ms_per_step": r["ms_per_step"],
                      "sweep_ms": r["sweep_ms_avg"],
                      "sweep_hbm_gbs_algorithmic": 2 * 5 * b * cells / (r["sweep_ms_avg"] * 1e-3) / 1e9,
+                     "zchunk": r["zchunk"],
                      "l1_rel_vs_vanleer_fp64_per_field": diff.cpu().numpy().tolist(),
                      "speedup_vs_vanleer_fp64": runs["vanleer_fp64"]["wall_s"] / r["wall_s"]}
     out["monotone_stencil_fraction"] = monotone_fraction(torch, runs["learned_fp32"]["state"][:, :, :, :], 1.4)
@@ -145,6 +151,19 @@ def recorded_traffic(form):
                     return None
                 return rec.get(f"{form}_bytes")
     except OSError:
+        return None
+    return None
+
+
+def recorded_flops():
+    """Algorithmic FP64 flops of one Sedov zone-cycle from the committed op-count record (the
+    oracle's own operations, each face flux counted once), or None."""
+    path = os.path.join(ROOT, "profiles", "sweep_sedov256_flops.md")
+    try:
+        for line in open(path):
+            if line.startswith("FLOPS_JSON"):
+                return json.loads(line.split("FLOPS_JSON", 1)[1])["per_zone_cycle"]["flops"]
+    except (OSError, KeyError, ValueError):
         return None
     return None
 
@@ -227,7 +246,7 @@ def main():
     for form in [f.strip() for f in args.forms.split(",") if f.strip()]:
         r = run_form(hydro, torch, prob, form, args.steps, args.warmup, args.zchunk)
         log(f"{form}: {r['ms_per_step']:.3f} ms/step, sweep {r['sweep_ms_avg']:.3f} ms "
-            f"(min {r['sweep_ms_min']:.3f}), {cells * args.steps / r['wall_s']:.3e} zone-cycles/s")
+            f"(min {r['sweep_ms_min']:.3f}), {cells * args.steps / r['wall_s']:.3e} zone-cycles/s, kz {r['zchunk']}")
         results[form] = r
 
     learned_out = None
@@ -259,6 +278,7 @@ def main():
             "ms_per_step": r["ms_per_step"],
             "sweep_ms": r["sweep_ms_avg"],
             "sweep_hbm_gbs_algorithmic": 2 * nvar * b * cells / (r["sweep_ms_avg"] * 1e-3) / 1e9,
+            "zchunk": r["zchunk"],
             "speedup_vs_fp64": (results["fp64"]["wall_s"] / r["wall_s"]) if "fp64" in results else None,
         }
     if l1 is not None:
@@ -276,7 +296,15 @@ def main():
         log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
         del src, dst
 
-    traffic_bytes = recorded_traffic(head["form"]) if (args.n == 256 and args.workload == "sedov") else None
+    sedov256 = args.n == 256 and args.workload == "sedov"
+    traffic_bytes = recorded_traffic(head["form"]) if sedov256 else None
+    flops_zc = recorded_flops() if sedov256 else None
+    alu = None
+    if flops_zc is not None:
+        peak = FP64_VECTOR_PEAK_TFLOPS if head["form"] == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+        tf = flops_zc * cells / (head["sweep_ms_avg"] * 1e-3) / 1e12
+        alu = {"achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+               "flops_per_zone_cycle": flops_zc, "algorithmic_flops_per_launch": flops_zc * cells}
     traffic = traffic_bytes / (head["sweep_ms_avg"] * 1e-3) / 1e9 if traffic_bytes else None
 
     cpu = None
@@ -304,7 +332,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "hx::sweep_kernel (fused MUSCL-Hancock sweep)",
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "alu": alu},
         "cpu_baseline": cpu,
         "forms": forms,
     }

@@ -123,8 +123,15 @@ hx_status hx_check(hx_ctx *ctx);
 /* Weights of the learned slope limiter, HX_MLP_NPARAM FP32 values (host), layout as above. */
 hx_status hx_set_mlp(hx_ctx *ctx, const float *h_w, size_t n);
 
-/* Tuning: z planes per workgroup of the 3D sweep (default 32).  Does not change results. */
+/* Tuning: z planes per workgroup of the 3D sweep; 0 (the default) chooses it at the first 3D step
+ * from the sweep's workgroups per compute unit and the number of compute units, so that the
+ * launch's dispatch rounds times the planes per workgroup is smallest.  Does not change results.
+ * HX_EINVAL for kz < 0. */
 hx_status hx_set_zchunk(hx_ctx *ctx, int kz);
+
+/* The z planes per workgroup in use: the value set, else the automatic choice (0 before the first
+ * 3D step).  HX_EINVAL for null arguments. */
+hx_status hx_get_zchunk(hx_ctx *ctx, int *kz);
 
 /* Enclosed-mass table of the last step that used HX_GRAVITY_POINT_MONOPOLE (n[0] doubles to the
  * host; synchronises).  For tests of the enclosed-mass reduction. */

@@ -218,7 +218,8 @@ struct hx_ctx {
     bool have_state = false;
     bool have_mlp = false;
     hx::Geo geo;
-    int kz = 32;
+    int kz = 0;       // z planes per workgroup set by hx_set_zchunk (0: automatic)
+    int kz_auto = 0;  // the automatic choice, made at the first 3D step
     double scale = 0.0;  // 4 pi / Omega_w
     bool dtpart_valid = false;  // the sweep's CFL maxima describe the current state
     long long dtpart_nb = 0;
@@ -400,20 +401,34 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     p.geo = x->geo;
     p.flag = at<int>(x, x->L.flag);
     p.dtpart = at<double>(x, x->L.dtpart);
-    p.kz = c.ndim == 3 ? (x->kz < c.n[2] ? x->kz : c.n[2]) : 1;
     p.mlp = at<float>(x, x->L.mlp);
     const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC;
     if (c.limiter == HX_LIMITER_MLP && !x->have_mlp)
         return fail(HX_ESTATE, "the learned limiter needs hx_set_mlp before stepping");
-    hipError_t e;
-    if (c.limiter == HX_LIMITER_MLP)
-        e = hx::launch_sweep_fp32_mlp(p, c.ndim, x->nvar, c.geom, x->stream);
-    else if (x->fp32)
-        e = spec ? hx::launch_sweep_fp32_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream)
-                 : hx::launch_sweep_fp32_generic(p, c.ndim, x->nvar, c.geom, x->stream);
-    else
-        e = spec ? hx::launch_sweep_fp64_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream)
-                 : hx::launch_sweep_fp64_generic(p, c.ndim, x->nvar, c.geom, x->stream);
+    // the instantiation for this configuration; with occ, only its workgroups per compute unit
+    auto sweep = [&](int* occ) -> hipError_t {
+        if (c.limiter == HX_LIMITER_MLP)
+            return hx::launch_sweep_fp32_mlp(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+        if (x->fp32)
+            return spec ? hx::launch_sweep_fp32_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream, occ)
+                        : hx::launch_sweep_fp32_generic(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+        return spec ? hx::launch_sweep_fp64_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream, occ)
+                    : hx::launch_sweep_fp64_generic(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+    };
+    if (c.ndim == 3 && x->kz == 0 && x->kz_auto == 0) {
+        int occ = 0, dev = 0, cus = 0;
+        p.kz = 1;
+        HIPCHECK(sweep(&occ));
+        HIPCHECK(hipGetDevice(&dev));
+        HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        if (occ < 1 || cus < 1)
+            return fail(HX_EHIP, "the sweep does not fit on a compute unit (occupancy %d)", occ);
+        const dim3 g = hx::sweep_grid(3, c.n, 1);
+        x->kz_auto = hx::choose_zchunk(c.n[2], (long long)g.x * g.y, (long long)occ * cus);
+    }
+    const int kz = x->kz > 0 ? x->kz : x->kz_auto;
+    p.kz = c.ndim == 3 ? (kz < c.n[2] ? kz : c.n[2]) : 1;
+    hipError_t e = sweep(nullptr);
     if (e != hipSuccess)
         return fail(HX_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     x->cur = 1 - x->cur;
@@ -608,9 +623,17 @@ hx_status hx_set_mlp(hx_ctx* x, const float* h_w, size_t n)
 
 hx_status hx_set_zchunk(hx_ctx* x, int kz)
 {
-    if (!x || kz < 1)
-        return fail(HX_EINVAL, "z chunk must be >= 1");
+    if (!x || kz < 0)
+        return fail(HX_EINVAL, "z chunk must be >= 0");
     x->kz = kz;
+    return HX_OK;
+}
+
+hx_status hx_get_zchunk(hx_ctx* x, int* kz)
+{
+    if (!x || !kz)
+        return fail(HX_EINVAL, "null argument");
+    *kz = x->kz > 0 ? x->kz : x->kz_auto;
     return HX_OK;
 }
 

@@ -138,11 +138,9 @@ template <typename R, int NV, int D>
 __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL, const R* qR, R* F)
 {
     using N = Num<R>;
-    R wL[NV], wR[NV], fL[NV], fR[NV];
+    R wL[NV], wR[NV];
     const R iL = to_prim<R, NV>(g, qL, wL);
     const R iR = to_prim<R, NV>(g, qR, wR);
-    phys_flux<R, NV, D>(wL, qL, fL);
-    phys_flux<R, NV, D>(wR, qR, fR);
     R rL = wL[0], rR = wR[0];
     R uL = wL[1 + D], uR = wR[1 + D];
     R pL = wL[4], pR = wR[4];
@@ -150,13 +148,16 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
     R cR = N::sqrt_(g.gamma * pR * iR);
     R SL = fmin(uL - cL, uR - cR);
     R SR = fmax(uL + cL, uR + cR);
-    if (SL >= R(0)) {
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            F[v] = fL[v];
-        return;
-    }
     if (solver == HX_HLL) {
+        R fL[NV], fR[NV];
+        phys_flux<R, NV, D>(wL, qL, fL);
+        phys_flux<R, NV, D>(wR, qR, fR);
+        if (SL >= R(0)) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                F[v] = fL[v];
+            return;
+        }
         if (SR <= R(0)) {
 #pragma unroll
             for (int v = 0; v < NV; v++)
@@ -169,28 +170,31 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
             F[v] = (SR * fL[v] - SL * fR[v] + SL * SR * (qR[v] - qL[v])) * inv;
         return;
     }
+    // HLLC: F_L for S_L >= 0, F_L + S_L (U*_L - U_L) for S_L < 0 <= S*, F_R + S_R (U*_R - U_R) for
+    // S* < 0 < S_R, F_R for S_R <= 0.  Every case needs the physical flux of one side only, so the
+    // side is chosen first.
     R mL = rL * (SL - uL);
     R mR = rR * (SR - uR);
     R Ss = N::div(pR - pL + uL * mL - uR * mR, mL - mR);
-    if (!(Ss >= R(0)) && !(SR > R(0))) {
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            F[v] = fR[v];
-        return;
-    }
-    const bool left = Ss >= R(0);
+    const bool left = SL >= R(0) || Ss >= R(0);
+    const bool star = !(SL >= R(0)) && (Ss >= R(0) || SR > R(0));
     R S = left ? SL : SR;
     R m = left ? mL : mR;
     R iv = left ? iL : iR;
-    R us[NV];
-    // select the star side through registers (no pointer selects, everything stays in VGPRs)
     R qs[NV], ws[NV], fs[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         qs[v] = left ? qL[v] : qR[v];
         ws[v] = left ? wL[v] : wR[v];
-        fs[v] = left ? fL[v] : fR[v];
     }
+    phys_flux<R, NV, D>(ws, qs, fs);
+    if (!star) {
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            F[v] = fs[v];
+        return;
+    }
+    R us[NV];
     R un = ws[1 + D];
     R fac = N::div(m, S - Ss);
     us[0] = fac;
@@ -220,6 +224,14 @@ __device__ __forceinline__ R limit(int lim, R a, R b)
     if (lim == HX_LIM_VANALBADA)
         return N::div(a * b * (a + b), a * a + b * b);
     return N::div(R(2) * a * b, a + b);
+}
+
+// Makes x opaque to the optimiser (emits no instruction): expressions of x before and after are
+// not merged, so a recomputation is not replaced by values kept in registers.
+template <typename T>
+__device__ __forceinline__ void opaque(T& x)
+{
+    asm volatile("" : "+v"(x));
 }
 
 // 16-lane row shifts (DPP row_shr:1 / row_shl:1): lane l of each row of 16 receives the value of

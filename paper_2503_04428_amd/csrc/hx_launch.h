@@ -35,11 +35,13 @@ struct ShellParams {
     double G, Mc;
 };
 
-hipError_t launch_sweep_fp64_generic(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
-hipError_t launch_sweep_fp64_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
-hipError_t launch_sweep_fp32_generic(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
-hipError_t launch_sweep_fp32_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
-hipError_t launch_sweep_fp32_mlp(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s);
+// Fused sweep launchers.  With occ != nullptr nothing is launched: *occ receives how many
+// workgroups of the instantiation that would run fit on one compute unit.
+hipError_t launch_sweep_fp64_generic(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
+hipError_t launch_sweep_fp64_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
+hipError_t launch_sweep_fp32_generic(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
+hipError_t launch_sweep_fp32_hllc_vl(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
+hipError_t launch_sweep_fp32_mlp(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_dt_final(const double* partial, int nb, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_dt(const DtParams& p, bool fp32, int nblocks, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_totals(const DtParams& p, bool fp32, int nblocks, double* out, hipStream_t s);
@@ -70,6 +72,36 @@ inline long long sweep_nblocks(int ndim, const int n[3], int kz)
 {
     dim3 g = sweep_grid(ndim, n, kz);
     return (long long)g.x * g.y * g.z;
+}
+
+// z planes per workgroup of a 3D sweep.  A workgroup marches kz + 2 predictor planes (plus about
+// one plane's worth of start-up loads), and the ceil(tiles * ceil(n2 / kz) / slots) dispatch
+// rounds of a launch, slots = resident workgroups of the whole chip, run one after the other, so
+// the launch costs about rounds * (kz + 3) plane steps.  Tiles differ in cost (the learned
+// limiter's network runs where the flow is monotone, divisions are skipped where it is flat), so
+// at least MIN_ROUNDS rounds are kept for the hardware's dynamic dispatch to even them out.  The kz
+// that minimises the cost under that constraint (the larger on a tie) is taken.
+inline int choose_zchunk(int n2, long long tiles, long long slots)
+{
+    constexpr long long MIN_ROUNDS = 4;
+    if (slots < 1)
+        slots = 1;
+    int best = 0;
+    double best_cost = 1e300;
+    for (int pass = 0; pass < 2 && best == 0; pass++) {
+        for (int kz = 4; kz <= n2; kz++) {
+            const long long nch = (n2 + kz - 1) / kz;
+            const long long rounds = (tiles * nch + slots - 1) / slots;
+            if (pass == 0 && rounds < MIN_ROUNDS)
+                continue;  // the second pass drops the constraint when no kz can meet it
+            const double cost = (double)rounds * (kz + 3);
+            if (cost <= best_cost) {
+                best_cost = cost;
+                best = kz;
+            }
+        }
+    }
+    return best > 0 ? best : (n2 < 32 ? n2 : 32);
 }
 
 }  // namespace hx

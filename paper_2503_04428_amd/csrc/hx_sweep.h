@@ -20,17 +20,29 @@
 
 namespace hx {
 
-// Minimum waves per SIMD the register allocator must allow (launch-bound hint); overridable at
-// build time per precision.  More waves hide more latency but may force register spills.
-#ifndef HX_MINW_FP64
-#define HX_MINW_FP64 1
-#endif
+// Minimum waves per SIMD the register allocator must allow (launch-bound hint).  More waves hide
+// more latency but may force register spills.  FP32 sweeps: HX_MINW_FP32.  FP64 3D sweeps: two
+// waves up to HX_MINW2_FP64_NV fields (measured on the 256^3 workloads: 5 fields 1.47 vs 1.98 ms,
+// 6 fields 1.42 vs 1.46 ms), one wave above (7 fields need ~330 registers); an explicit
+// HX_MINW_FP64 overrides both.
 #ifndef HX_MINW_FP32
 #define HX_MINW_FP32 3
 #endif
-template <typename R>
+#ifndef HX_MINW2_FP64_NV
+#define HX_MINW2_FP64_NV 6
+#endif
+// FP64 sweeps: form the limited slopes again for the face states (1) or hold them (0)
+#ifndef HX_RESLOPE_FP64
+#define HX_RESLOPE_FP64 0
+#endif
+template <typename R, int NV, int NDIM>
 struct MinWaves {
-    static constexpr int value = sizeof(R) == 8 ? HX_MINW_FP64 : HX_MINW_FP32;
+#ifdef HX_MINW_FP64
+    static constexpr int fp64 = HX_MINW_FP64;
+#else
+    static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV ? 2 : 1;
+#endif
+    static constexpr int value = sizeof(R) == 8 ? fp64 : HX_MINW_FP32;
 };
 
 template <int NDIM>
@@ -126,7 +138,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // limiter with HLLC (slope stencil of half-width 2, BF16 matrix-core network); SPEC = 0 reads the
 // limiter and the Riemann solver from the parameters.
 template <typename R, int NV, int NDIM, int GEOM, int SPEC>
-__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::value)
+__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM>::value))
     sweep_kernel(const SweepParams p)
 {
     using N = Num<R>;
@@ -525,6 +537,27 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
         };
         R dlt[3][NV];  // half increments of the limited slopes
         R du[NV];
+        // FP64 sweeps form the limited slopes again where the face states are built instead of
+        // holding 3 NV of them across the predictor (the register budget of two waves per SIMD)
+        constexpr bool RESLOPE = !MLP && sizeof(R) == 8 && HX_RESLOPE_FP64;
+        R cm3[3] = {cmx, cmy, cmz}, cp3[3] = {cpx, cpy, cpz};
+        auto slope_of = [&](int d, R* dl) {
+            slopes([&](int j, int v) { return stv(d, j, v); }, cm3[d], cp3[d], dl);
+        };
+        // inputs of slope_of made opaque, so that it is evaluated again rather than kept
+        auto reslope_fence = [&]() {
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                opaque(cm3[d]);
+                opaque(cp3[d]);
+            }
+#pragma unroll
+            for (int j = 0; j < 2 * S + 1; j++)
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    opaque(wz[j][v]);
+        };
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             du[v] = R(0);
@@ -609,14 +642,24 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
         }
         // positivity of all half-step face states; otherwise first order for this cell
         bool bad = false;
+        if constexpr (RESLOPE)
+            reslope_fence();
 #pragma unroll
         for (int d = 0; d < NDIM; d++) {
+            R dd[NV];
+            if constexpr (RESLOPE) {
+                slope_of(d, dd);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    dd[v] = dlt[d][v];
+            }
 #pragma unroll
             for (int side = 0; side < 2; side++) {
                 R ws[NV], qs[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    ws[v] = side ? wcur[v] + dlt[d][v] : wcur[v] - dlt[d][v];
+                    ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
                 to_cons<R, NV>(gas, ws, qs);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -631,12 +674,36 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
                 dlt[0][v] = dlt[1][v] = dlt[2][v] = R(0);
             }
         }
+        // The face states are formed again below, one axis at a time just before its flux, so
+        // that few are held at once; the opaque copies keep the compiler from carrying the six
+        // states of the check over instead.
+        if constexpr (RESLOPE) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                opaque(du[v]);
+            reslope_fence();
+        }
+        // limited slopes of axis d for the face states (zero in the fallback)
+        auto axis_dl = [&](int d, R* dd) {
+            if constexpr (RESLOPE) {
+                slope_of(d, dd);
+                if (bad) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        dd[v] = R(0);
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    dd[v] = dlt[d][v];
+            }
+        };
         // final half-step face states: cons(W -/+ delta) + du (or cons(W) in the fallback)
-        auto face_state = [&](int d, int side, R* out) {
+        auto face_state = [&](const R* dd, int side, R* out) {
             R ws[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                ws[v] = side ? wcur[v] + dlt[d][v] : wcur[v] - dlt[d][v];
+                ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
             to_cons<R, NV>(gas, ws, out);
             if (!bad) {
 #pragma unroll
@@ -644,74 +711,45 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
                     out[v] += du[v];
             }
         };
-        R uh[NV];  // cell half-step state for the sources
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            uh[v] = bad ? qcur[v] : qcur[v] + du[v];
-
-        R qmx[NV], qpx[NV];
-        face_state(0, 0, qmx);
-        face_state(0, 1, qpx);
-        R qmy[NV];
-        if (NDIM >= 2) {
-            R qpy[NV];
-            face_state(1, 0, qmy);
-            face_state(1, 1, qpy);
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                sFy[v][tid] = qpy[v];
-        }
-        R qmz[NV], qpz[NV];
-        if (NDIM == 3) {
-            face_state(2, 0, qmz);
-            face_state(2, 1, qpz);
-        }
-        __syncthreads();
-
-        // -------------------------------------------------------------- fluxes
-        const bool plane_live = NDIM < 3 || (k >= k0 && k < k1);
-        R Fx[NV], Fy[NV], Fz[NV];
+        // sources of the cell half-step state uh = U^n + du (U^n in the fallback): gravity
+        // (0, rho g, m.g) now; the spherical terms keep uh for the update
+        R uh[GEOM == HX_SPH ? NV : 1];
+        double Sg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         {
-            R L[NV];
+            R u[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                L[v] = from_left<BX>(qpx[v]);
-            if (tx == 0) {
+                u[v] = bad ? qcur[v] : qcur[v] + du[v];
+            if (p.gravity != HX_GRAV_NONE) {
+                Sg[1] = (double)u[0] * g[0];
+                Sg[2] = (double)u[0] * g[1];
+                Sg[3] = (double)u[0] * g[2];
+                Sg[4] = (double)u[1] * g[0] + (double)u[2] * g[1] + (double)u[3] * g[2];
+            }
+            if constexpr (GEOM == HX_SPH) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    L[v] = qmx[v];
+                    uh[v] = u[v];
             }
-            riemann<R, NV, 0>(solver, gas, L, qmx, Fx);
         }
-        if (NDIM >= 2) {
-            R L[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                L[v] = ty > 0 ? sFy[v][tid - BX] : qmy[v];
-            riemann<R, NV, 1>(solver, gas, L, qmy, Fy);
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                sGy[v][tid] = Fy[v];
-        }
+
+        // -------------------------------------------------------------- fluxes and update
+        // Order: (3D) z flux and the end of plane k-1, then the x flux and the x terms of plane k,
+        // then the y exchange; every cell still sums U^n + x terms + y terms (+ z terms) and then
+        // its sources, as the update equation is written.
+        const bool plane_live = NDIM < 3 || (k >= k0 && k < k1);
         if (NDIM == 3) {
-            riemann<R, NV, 2>(solver, gas, uzp, qmz, Fz);
-        }
-        __syncthreads();
-
-        // -------------------------------------------------------------- update
-        R Fxr[NV], Fyu[NV];
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            Fxr[v] = from_right<BX>(Fx[v]);
-        if (NDIM >= 2) {
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                Fyu[v] = ty < BY - 1 ? sGy[v][tid + BX] : Fy[v];
-        }
-
-        if (interior) {
+            // z: the +z state of plane k-1 is held by the thread; plane k's replaces it
+            R Fz[NV];
+            {
+                R dd[NV], qmz[NV];
+                axis_dl(2, dd);
+                face_state(dd, 0, qmz);
+                riemann<R, NV, 2>(solver, gas, uzp, qmz, Fz);
+                face_state(dd, 1, uzp);
+            }
             // finish plane k-1 with its z terms and sources, then store it
-            if (NDIM == 3 && k - 1 >= k0) {
+            if (interior && k - 1 >= k0) {
                 const int kp = k - 1;
                 if (GEOM == HX_CART) {
                     const R mu = N::from_d(dtd / p.geo.w[2][kp + ng]);
@@ -750,117 +788,175 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, MinWaves<R>::v
                     p.flag[0] = 1;
                 smax = fmax(smax, sr);
             }
-            if (plane_live) {
-                // x and y terms of plane k
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                fzlo[v] = Fz[v];
+        }
+        R Fx[NV], Fxr[NV];
+        {
+            // x: the +x state of the left neighbour arrives by a row shift
+            R qmx[NV], L[NV];
+            {
+                R dd[NV], qpx[NV];
+                axis_dl(0, dd);
+                face_state(dd, 1, qpx);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    acc[v] = qcur[v];
-                double dV = 0.0, dSrm = 0.0, dSrp = 0.0, dStm = 0.0, dStp = 0.0, dph = 1.0;
+                    L[v] = from_left<BX>(qpx[v]);
+                face_state(dd, 0, qmx);
+            }
+            if (tx == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    L[v] = qmx[v];
+            }
+            riemann<R, NV, 0>(solver, gas, L, qmx, Fx);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                Fxr[v] = from_right<BX>(Fx[v]);
+        }
+        // x terms of plane k (and the spherical x parts of its sources)
+        const bool upd = interior && plane_live;
+        double dV = 0.0, dSrm = 0.0, dSrp = 0.0, dStm = 0.0, dStp = 0.0, dph = 1.0, cr = 0.0;
+        double Trt = 0.0, Trp = 0.0;
+        if (upd) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                acc[v] = qcur[v];
+            if (GEOM == HX_CART) {
+                const R mu = N::from_d(dtd / wx);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    acc[v] += mu * (Fx[v] - Fxr[v]);
+            } else {
+                const int kin = NDIM == 3 ? k : 0;
+                dph = p.geo.w[2][NDIM == 3 ? kin + ng : 0];
+                const double ctj = p.geo.ct[jj];
+                dV = p.geo.vr[ii] * ctj * dph;
+                const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
+                dSrm = rm * rm * ctj * dph;
+                dSrp = rp * rp * ctj * dph;
+                const double kvd = dtd / dV;
+                const R kv = N::from_d(kvd);
+                const R sm = N::from_d(dSrm), sp = N::from_d(dSrp);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    acc[v] += kv * (Fx[v] * sm - Fxr[v] * sp);
+                cr = (rp - rm) / ((rp + rm) * dV);
+                Trt = -cr * ((double)Fxr[2] * dSrp + (double)Fx[2] * dSrm);
+                Trp = -cr * ((double)Fxr[3] * dSrp + (double)Fx[3] * dSrm);
+            }
+        }
+
+        // y: +y states through LDS, then the fluxes of the upper faces through LDS
+        R Fy[NV], Fyu[NV];
+        {
+            R qmy[NV];
+            if (NDIM >= 2) {
+                R dd[NV], qpy[NV];
+                axis_dl(1, dd);
+                face_state(dd, 0, qmy);
+                face_state(dd, 1, qpy);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    sFy[v][tid] = qpy[v];
+            }
+            __syncthreads();
+            if (NDIM >= 2) {
+                R L[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    L[v] = ty > 0 ? sFy[v][tid - BX] : qmy[v];
+                riemann<R, NV, 1>(solver, gas, L, qmy, Fy);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    sGy[v][tid] = Fy[v];
+            }
+            __syncthreads();
+            if (NDIM >= 2) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    Fyu[v] = ty < BY - 1 ? sGy[v][tid + BX] : Fy[v];
+            }
+        }
+
+        if (upd) {
+            // y terms of plane k
+            if (NDIM >= 2) {
                 if (GEOM == HX_CART) {
-                    const R mu = N::from_d(dtd / wx);
+                    const R muy = N::from_d(dtd / wy);
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        acc[v] += mu * (Fx[v] - Fxr[v]);
-                    if (NDIM >= 2) {
-                        const R muy = N::from_d(dtd / wy);
-#pragma unroll
-                        for (int v = 0; v < NV; v++)
-                            acc[v] += muy * (Fy[v] - Fyu[v]);
-                    }
+                        acc[v] += muy * (Fy[v] - Fyu[v]);
                 } else {
-                    const int kin = NDIM == 3 ? k : 0;
-                    dph = p.geo.w[2][NDIM == 3 ? kin + ng : 0];
-                    const double ctj = p.geo.ct[jj];
-                    dV = p.geo.vr[ii] * ctj * dph;
-                    const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
-                    dSrm = rm * rm * ctj * dph;
-                    dSrp = rp * rp * ctj * dph;
                     const double kvd = dtd / dV;
                     const R kv = N::from_d(kvd);
-                    const R sm = N::from_d(dSrm), sp = N::from_d(dSrp);
+                    dStm = p.geo.hr[ii] * p.geo.sf[jj] * dph;
+                    dStp = p.geo.hr[ii] * p.geo.sf[jj + 1] * dph;
+                    const R tm = N::from_d(dStm), tp = N::from_d(dStp);
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        acc[v] += kv * (Fx[v] * sm - Fxr[v] * sp);
-                    if (NDIM >= 2) {
-                        dStm = p.geo.hr[ii] * p.geo.sf[jj] * dph;
-                        dStp = p.geo.hr[ii] * p.geo.sf[jj + 1] * dph;
-                        const R tm = N::from_d(dStm), tp = N::from_d(dStp);
-#pragma unroll
-                        for (int v = 0; v < NV; v++)
-                            acc[v] += kv * (Fy[v] * tm - Fyu[v] * tp);
-                    }
+                        acc[v] += kv * (Fy[v] * tm - Fyu[v] * tp);
                 }
-                // sources of plane k (finished now in 1D/2D, after the z terms in 3D)
-                double S[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                if (p.gravity != HX_GRAV_NONE) {
-                    S[1] = (double)uh[0] * g[0];
-                    S[2] = (double)uh[0] * g[1];
-                    S[3] = (double)uh[0] * g[2];
-                    S[4] = (double)uh[1] * g[0] + (double)uh[2] * g[1] + (double)uh[3] * g[2];
+            }
+            // sources of plane k (finished now in 1D/2D, after the z terms in 3D)
+            double S[5] = {0.0, Sg[1], Sg[2], Sg[3], Sg[4]};
+            if (GEOM == HX_SPH) {
+                const double grg = (dSrp - dSrm) / dV;
+                double pu = 0.0;
+                if (NDIM < 3) {
+                    R wu[NV];
+                    to_prim<R, NV>(gas, uh, wu);
+                    pu = (double)wu[4];
                 }
-                if (GEOM == HX_SPH) {
-                    const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
-                    const double cr = (rp - rm) / ((rp + rm) * dV);
-                    const double grg = (dSrp - dSrm) / dV;
-                    double pu = 0.0;
-                    if (NDIM < 3) {
-                        R wu[NV];
-                        to_prim<R, NV>(gas, uh, wu);
-                        pu = (double)wu[4];
-                    }
-                    double Xt, Tt = 0.0, gtg = 0.0;
-                    if (NDIM >= 2) {
-                        const double smm = p.geo.sf[jj], spp = p.geo.sf[jj + 1];
-                        const double ctc = (spp - smm) / ((spp + smm) * dV);
-                        gtg = (dStp - dStm) / dV;
-                        Xt = 0.5 * ((double)Fy[2] + (double)Fyu[2]);
-                        Tt = -ctc * ((double)Fyu[3] * dStp + (double)Fy[3] * dStm);
-                    } else {
-                        Xt = (double)uh[2] * ((double)uh[2] / (double)uh[0]) + pu;
-                    }
-                    const double Trt = -cr * ((double)Fxr[2] * dSrp + (double)Fx[2] * dSrm);
-                    const double Trp = -cr * ((double)Fxr[3] * dSrp + (double)Fx[3] * dSrm);
-                    if (NDIM == 3) {
-                        sph_t[0] = Trt;
-                        sph_t[1] = Trp;
-                        sph_t[2] = Tt;
-                        sph_t[3] = Xt;
-                        sph_t[4] = grg;
-                        sph_t[5] = gtg;
-                    } else {
-                        const double Xp = (double)uh[3] * ((double)uh[3] / (double)uh[0]) + pu;
-                        S[1] = S[1] + 0.5 * (Xt + Xp) * grg;
-                        S[2] = S[2] + (Trt + Xp * gtg);
-                        S[3] = S[3] + (Trp + Tt);
-                    }
+                double Xt, Tt = 0.0, gtg = 0.0;
+                if (NDIM >= 2) {
+                    const double smm = p.geo.sf[jj], spp = p.geo.sf[jj + 1];
+                    const double ctc = (spp - smm) / ((spp + smm) * dV);
+                    gtg = (dStp - dStm) / dV;
+                    Xt = 0.5 * ((double)Fy[2] + (double)Fyu[2]);
+                    Tt = -ctc * ((double)Fyu[3] * dStp + (double)Fy[3] * dStm);
+                } else {
+                    Xt = (double)uh[2] * ((double)uh[2] / (double)uh[0]) + pu;
                 }
                 if (NDIM == 3) {
+                    sph_t[0] = Trt;
+                    sph_t[1] = Trp;
+                    sph_t[2] = Tt;
+                    sph_t[3] = Xt;
+                    sph_t[4] = grg;
+                    sph_t[5] = gtg;
+                } else {
+                    const double Xp = (double)uh[3] * ((double)uh[3] / (double)uh[0]) + pu;
+                    S[1] = S[1] + 0.5 * (Xt + Xp) * grg;
+                    S[2] = S[2] + (Trt + Xp * gtg);
+                    S[3] = S[3] + (Trp + Tt);
+                }
+            }
+            if (NDIM == 3) {
+#pragma unroll
+                for (int v = 1; v < 5; v++)
+                    sg[v] = S[v];
+            } else {
+                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
 #pragma unroll
                     for (int v = 1; v < 5; v++)
-                        sg[v] = S[v];
-                } else {
-                    if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
-#pragma unroll
-                        for (int v = 1; v < 5; v++)
-                            acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
-                    }
-                    const long long off = ((long long)jj * n0) + ii;
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        Un[(long long)v * p.plane + off] = acc[v];
-                    double wd[3] = {wx, wy, 0.0};
-                    const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
-                    if (sr < 0.0)
-                        p.flag[0] = 1;
-                    smax = fmax(smax, sr);
+                        acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
                 }
+                const long long off = ((long long)jj * n0) + ii;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    Un[(long long)v * p.plane + off] = acc[v];
+                double wd[3] = {wx, wy, 0.0};
+                const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
+                if (sr < 0.0)
+                    p.flag[0] = 1;
+                smax = fmax(smax, sr);
             }
         }
         if (NDIM == 3) {
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                fzlo[v] = Fz[v];
-                uzp[v] = qpz[v];
 #pragma unroll
                 for (int j = 0; j < 2 * S; j++)
                     wz[j][v] = wz[j + 1][v];

@@ -4,9 +4,9 @@
 
 namespace hx {
 
-hipError_t launch_sweep_fp32_mlp(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s)
+hipError_t launch_sweep_fp32_mlp(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ)
 {
-    return launch_sweep_mlp_t<float>(p, ndim, nvar, geom, s);
+    return launch_sweep_mlp_t<float>(p, ndim, nvar, geom, s, occ);
 }
 
 }  // namespace hx

@@ -53,7 +53,7 @@ _lib = None
 # names of the exported entry points, as declared in include/hydro.h
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
            "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
-           "hx_set_zchunk", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
+           "hx_set_zchunk", "hx_get_zchunk", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
            "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_adam", "hx_last_error", "hx_destroy"]
 
 
@@ -81,6 +81,7 @@ def load_library():
     L.hx_check.argtypes = [vp]
     L.hx_set_mlp.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
     L.hx_set_zchunk.argtypes = [vp, C.c_int]
+    L.hx_get_zchunk.argtypes = [vp, C.POINTER(C.c_int)]
     L.hx_enclosed_mass.argtypes = [vp, _DP]
     L.hx_mlp_eval.argtypes = [vp, vp, C.c_longlong, vp, vp]
     L.hx_mlp_features.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, vp]
@@ -249,7 +250,14 @@ class Solver:
         self._call(self.L.hx_set_mlp(self.ctx, w.ctypes.data_as(C.POINTER(C.c_float)), C.c_size_t(w.size)))
 
     def set_zchunk(self, kz: int):
+        """z planes per workgroup of the 3D sweep (0: automatic)."""
         self._call(self.L.hx_set_zchunk(self.ctx, int(kz)))
+
+    def zchunk(self) -> int:
+        """z planes per workgroup in use (0 before the first automatic 3D step)."""
+        v = C.c_int(0)
+        self._call(self.L.hx_get_zchunk(self.ctx, C.byref(v)))
+        return v.value
 
     def enclosed_mass(self) -> np.ndarray:
         out = np.zeros(int(_get(self.prob, "n")[0]))
