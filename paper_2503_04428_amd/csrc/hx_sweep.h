@@ -355,10 +355,18 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     if constexpr (MLP)
         mlp_fill_shared(p.mlp, tid, NT, sMlp);
     // limited half increments of one axis; st(j, v) = primitive v at offset j - 2 along the axis
+    // (all stencil values are read before the first limiter branch, so that their loads overlap)
     auto slopes = [&](auto&& st, R cm, R cp, R* dl) {
+        R a[NV], b[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const R w1 = st(1, v), w2 = st(2, v), w3 = st(3, v);
+            a[v] = cm * (w2 - w1);
+            b[v] = cp * (w3 - w2);
+        }
 #pragma unroll
         for (int v = 0; v < NV; v++)
-            dl[v] = limit<R>(lim, cm * (st(2, v) - st(1, v)), cp * (st(3, v) - st(2, v)));
+            dl[v] = limit<R>(lim, a[v], b[v]);
     };
     // learned form of slopes() for the axes a0 .. a0+na-1 (na <= 2); st(a, j, v) = primitive v at
     // offset j - 2 along axis a.  The stencils are read again after the queue fence, so that they
@@ -453,6 +461,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     R uzp[NV];     // +z half-step state of plane k-1
     double sg[5];  // gravity source of plane k-1 (components 1..4)
     double sph_t[6];  // spherical partial sources of plane k-1: Trt, Trp, Tt, Xt, grg, gtg
+    double w2prev = 0.0;  // z width of plane k-1 (loaded for its predictor; the kernel's own stores
+                          // would force the finish of the plane to load it again from memory)
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         acc[v] = R(0);
@@ -516,6 +526,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         // -------------------------------------------------------------- predictor, plane k
         bool fzk = false;
         int kk = 0, gz = 0;
+        double w2k = 0.0;  // z width of plane k
         R cmz = R(0), cpz = R(0), lamz = R(0);
         double g[3] = {gcol[0], gcol[1], gcol[2]};
         if (NDIM == 3) {
@@ -524,7 +535,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             gz = kc + ng;
             cmz = N::from_d(p.geo.cm[2][gz]);
             cpz = N::from_d(p.geo.cp[2][gz]);
-            double wz = GEOM == HX_CART ? p.geo.w[2][gz] : p.geo.rabs[gx] * p.geo.sabs[gy] * p.geo.w[2][gz];
+            w2k = p.geo.w[2][gz];
+            double wz = GEOM == HX_CART ? w2k : p.geo.rabs[gx] * p.geo.sabs[gy] * w2k;
             lamz = N::from_d(dtd / (2.0 * wz));
             if (fzk && p.gravity == HX_GRAV_UNIFORM)
                 g[2] = -g[2];
@@ -770,12 +782,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             if (interior && k - 1 >= k0) {
                 const int kp = k - 1;
                 if (GEOM == HX_CART) {
-                    const R mu = N::from_d(dtd / p.geo.w[2][kp + ng]);
+                    const R mu = N::from_d(dtd / w2prev);
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += mu * (fzlo[v] - Fz[v]);
                 } else {
-                    const double dph = p.geo.w[2][kp + ng];
+                    const double dph = w2prev;
                     const double dV = p.geo.vr[ii] * p.geo.ct[jj] * dph;
                     const R kv = N::from_d(dtd / dV);
                     const R dS = N::from_d(p.geo.hr[ii] * p.geo.w[1][jj + ng]);
@@ -799,8 +811,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     Un[(long long)v * p.plane + off] = acc[v];
-                double wd[3] = {wx, wy, GEOM == HX_CART ? p.geo.w[2][kp + ng]
-                                                        : p.geo.rabs[gx] * p.geo.sabs[gy] * p.geo.w[2][kp + ng]};
+                double wd[3] = {wx, wy, GEOM == HX_CART ? w2prev : p.geo.rabs[gx] * p.geo.sabs[gy] * w2prev};
                 const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
                 if (sr < 0.0)
                     p.flag[0] = 1;
@@ -848,7 +859,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     acc[v] += mu * (Fx[v] - Fxr[v]);
             } else {
                 const int kin = NDIM == 3 ? k : 0;
-                dph = p.geo.w[2][NDIM == 3 ? kin + ng : 0];
+                dph = NDIM == 3 ? w2k : p.geo.w[2][0];
                 const double ctj = p.geo.ct[jj];
                 dV = p.geo.vr[ii] * ctj * dph;
                 const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
@@ -973,6 +984,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             }
         }
         if (NDIM == 3) {
+            w2prev = w2k;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
 #pragma unroll
