@@ -39,6 +39,7 @@ typedef struct {
     int n[3];
     double gm1;       /* gamma - 1 */
     double inv_gm1;   /* 1 / (gamma - 1) */
+    int de;           /* 1: the last field is the monitored internal energy e */
     double *gr;       /* radial gravity per interior shell (point / monopole), or NULL */
 } Ctx;
 
@@ -205,8 +206,12 @@ static double prim_inv(const Ctx *x, const double *q, double *w)
     w[2] = u2;
     w[3] = u3;
     w[4] = x->gm1 * (q[4] - ke);
-    for (int v = 5; v < x->nvar; v++)
+    for (int v = 5; v < x->nvar - x->de; v++)
         w[v] = q[v] * inv;
+    /* the internal energy is reconstructed per unit volume, like the pressure, so that it stays
+     * constant across a contact (reading) */
+    if (x->de)
+        w[x->nvar - 1] = q[x->nvar - 1];
     return inv;
 }
 
@@ -220,8 +225,10 @@ static void cons(const Ctx *x, const double *w, double *q)
     q[2] = rho * w[2];
     q[3] = rho * w[3];
     q[4] = w[4] * x->inv_gm1 + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
-    for (int v = 5; v < x->nvar; v++)
+    for (int v = 5; v < x->nvar - x->de; v++)
         q[v] = rho * w[v];
+    if (x->de)
+        q[x->nvar - 1] = w[x->nvar - 1];
 }
 
 static double pressure_of(const Ctx *x, const double *q)
@@ -232,7 +239,7 @@ static double pressure_of(const Ctx *x, const double *q)
 }
 
 /* physical flux along axis d of a state given by primitives w and conserved q */
-static void phys_flux(int nvar, int d, const double *w, const double *q, double *f)
+static void phys_flux(int nvar, int de, int d, const double *w, const double *q, double *f)
 {
     double un = w[1 + d];
     double mn = q[1 + d];
@@ -242,25 +249,30 @@ static void phys_flux(int nvar, int d, const double *w, const double *q, double 
     f[3] = mn * w[3];
     f[1 + d] = f[1 + d] + w[4];
     f[4] = un * (q[4] + w[4]);
-    for (int v = 5; v < nvar; v++)
+    for (int v = 5; v < nvar - de; v++)
         f[v] = mn * w[v];
+    if (de)
+        f[nvar - 1] = un * w[nvar - 1];  /* u e */
 }
 
 /* HLL and HLLC fluxes with Davis wave-speed estimates (Sect. 3.2; the solvers are those of
  * Toro's textbook, which the paper cites for them). */
-static void riemann(int solver, int d, int nvar, double gamma, double gm1, const double *qL,
-                    const double *qR, double *F)
+/* uf (if not NULL) receives the velocity of the interface: the upwind side's normal velocity
+ * outside the star region, the contact speed S* inside it (HLLC; HLL leaves it unset). */
+static void riemann(int solver, int d, int nvar, int de, double gamma, double gm1, const double *qL,
+                    const double *qR, double *F, double *uf)
 {
     Ctx x;
     memset(&x, 0, sizeof x);
     x.nvar = nvar;
+    x.de = de;
     x.gm1 = gm1;
     x.inv_gm1 = 1.0 / gm1;
     double wL[MAXV], wR[MAXV], fL[MAXV], fR[MAXV];
     double iL = prim_inv(&x, qL, wL);
     double iR = prim_inv(&x, qR, wR);
-    phys_flux(nvar, d, wL, qL, fL);
-    phys_flux(nvar, d, wR, qR, fR);
+    phys_flux(nvar, de, d, wL, qL, fL);
+    phys_flux(nvar, de, d, wR, qR, fR);
     double rL = wL[0], rR = wR[0];
     double uL = wL[1 + d], uR = wR[1 + d];
     double pL = wL[4], pR = wR[4];
@@ -272,6 +284,8 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
     if (SL >= 0.0) {
         for (int v = 0; v < nvar; v++)
             F[v] = fL[v];
+        if (uf)
+            *uf = uL;
         return;
     }
     if (solver == OR_HLL) {
@@ -298,8 +312,12 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
     } else {
         for (int v = 0; v < nvar; v++)
             F[v] = fR[v];
+        if (uf)
+            *uf = uR;
         return;
     }
+    if (uf)
+        *uf = Ss;
     double un = w[1 + d];
     double fac = m / (S - Ss);
     double us[MAXV];
@@ -309,8 +327,10 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
     us[3] = fac * w[3];
     us[1 + d] = fac * Ss;
     us[4] = fac * (q[4] * iv + (Ss - un) * (Ss + w[4] / m));
-    for (int v = 5; v < nvar; v++)
+    for (int v = 5; v < nvar - de; v++)
         us[v] = fac * w[v];
+    if (de)
+        us[nvar - 1] = fac * (w[nvar - 1] * iv);  /* rho* e / rho of the side */
     for (int v = 0; v < nvar; v++)
         F[v] = f[v] + S * (us[v] - q[v]);
 }
@@ -318,7 +338,7 @@ static void riemann(int solver, int d, int nvar, double gamma, double gm1, const
 void or_riemann_flux(int solver, int d, int nvar, double gamma, const double *qL, const double *qR,
                      double *flux)
 {
-    riemann(solver, d, nvar, gamma, gamma - 1.0, qL, qR, flux);
+    riemann(solver, d, nvar, 0, gamma, gamma - 1.0, qL, qR, flux, NULL);
 }
 
 /* ------------------------------------------------------------------ limiters */
@@ -468,8 +488,10 @@ static int ctx_init(Ctx *x, const or_config *c)
 {
     memset(x, 0, sizeof *x);
     x->c = c;
-    x->nvar = 5 + c->nscalar;
+    x->nvar = 5 + c->nscalar + (c->dual_energy ? 1 : 0);
     if (c->ndim < 1 || c->ndim > 3 || c->nscalar < 0 || x->nvar > MAXV)
+        return OR_EINVAL;
+    if (c->dual_energy && (c->riemann != OR_HLLC || !(c->de_eps >= 0.0)))
         return OR_EINVAL;
     if (c->limiter == OR_LIM_MLP && (c->ng < 3 || !c->mlp))
         return OR_EINVAL;
@@ -489,6 +511,7 @@ static int ctx_init(Ctx *x, const or_config *c)
         return OR_EINVAL;
     x->gm1 = c->gamma - 1.0;
     x->inv_gm1 = 1.0 / x->gm1;
+    x->de = c->dual_energy ? 1 : 0;
     return OR_OK;
 }
 
@@ -616,6 +639,25 @@ static int box_grow(Box *b, const int lo[3], const int hi[3], const int act[3], 
 
 static long box_size(const Box *b) { return (long)b->ext[0] * b->ext[1] * b->ext[2]; }
 
+/* e_k = |m|^2 / (2 rho) of a conserved state */
+static double kinetic_energy(const double *q)
+{
+    return 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+}
+
+double or_de_alpha(double e, double ek, double eps)
+{
+    /* Sect. 2.4: 1 for e >= eps e_k, (e / (eps e_k))^2 down to eps e_k / 10, 0 below */
+    const double t = eps * ek;
+    if (e >= t)
+        return 1.0;
+    if (e > t / 10.0) {
+        const double r = e / t;
+        return r * r;
+    }
+    return 0.0;
+}
+
 int or_step_box(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
                 double *out)
 {
@@ -710,11 +752,15 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                     cons(&x, wm, um[d]);
                     cons(&x, wp, up[d]);
                     double fm[MAXV], fp[MAXV];
-                    phys_flux(nv, d, wm, um[d], fm);
-                    phys_flux(nv, d, wp, up[d], fp);
+                    phys_flux(nv, x.de, d, wm, um[d], fm);
+                    phys_flux(nv, x.de, d, wp, up[d], fp);
                     double lam = dt / (2.0 * width(c, d, i, j, k));
                     for (int v = 0; v < nv; v++)
                         du[v] += lam * (fm[v] - fp[v]);
+                    /* internal energy: - (dt/2) P div(u) with the reconstructed face velocities
+                     * and P = (gamma - 1) e of the cell (eq. pressure_fix; reading) */
+                    if (c->dual_energy)
+                        du[nv - 1] += lam * ((x.gm1 * q[nv - 1]) * (wm[1 + d] - wp[1 + d]));
                 }
                 if (c->gravity != OR_GRAV_NONE) {
                     double g[3], S[MAXV];
@@ -771,6 +817,9 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                 long iw = bidx(&bw, i, j, k);
                 long ip = bidx(&bp, i, j, k);
                 double acc[MAXV], Fm[3][MAXV], Fp[3][MAXV];
+                double ufm = 0.0, ufp = 0.0;  /* interface velocities (internal energy) */
+                /* P of the cell's half-step internal energy, like the other sources (reading) */
+                const double pe = c->dual_energy ? x.gm1 * UH[(nv - 1) * np + ip] : 0.0;
                 for (int v = 0; v < nv; v++)
                     acc[v] = Q[v * nw + iw];
                 for (int d = 0; d < 3; d++) {
@@ -786,19 +835,22 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                         L[v] = FS[((d * 2 + 1) * nv + v) * np + ipm];
                         R[v] = FS[((d * 2 + 0) * nv + v) * np + ip];
                     }
-                    riemann(c->riemann, d, nv, c->gamma, x.gm1, L, R, Fm[d]);
+                    riemann(c->riemann, d, nv, x.de, c->gamma, x.gm1, L, R, Fm[d], &ufm);
                     for (int v = 0; v < nv; v++) {
                         L[v] = FS[((d * 2 + 1) * nv + v) * np + ip];
                         R[v] = FS[((d * 2 + 0) * nv + v) * np + ipq];
                     }
                     /* the upper face's flux is the next cell's lower-face flux once more */
                     OR_REPEATED_WORK(1);
-                    riemann(c->riemann, d, nv, c->gamma, x.gm1, L, R, Fp[d]);
+                    riemann(c->riemann, d, nv, x.de, c->gamma, x.gm1, L, R, Fp[d], &ufp);
                     OR_REPEATED_WORK(0);
                     if (c->geom == OR_CART) {
                         double mu = dt / dxc(c, d, cidx[d]);
                         for (int v = 0; v < nv; v++)
                             acc[v] += mu * (Fm[d][v] - Fp[d][v]);
+                        /* internal energy: - dt P div(u) with the interface velocities */
+                        if (c->dual_energy)
+                            acc[nv - 1] += mu * (pe * (ufm - ufp));
                     } else {
                         double dSm, dSp;
                         if (d == 0) {
@@ -814,6 +866,8 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                         double kv = dt / sph_dV(c, i, j, k);
                         for (int v = 0; v < nv; v++)
                             acc[v] += kv * (Fm[d][v] * dSm - Fp[d][v] * dSp);
+                        if (c->dual_energy)
+                            acc[nv - 1] += kv * (pe * (ufm * dSm - ufp * dSp));
                     }
                 }
                 /* sources, evaluated with the cell's half-step state */
@@ -867,6 +921,19 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                 if (have_src)
                     for (int v = 0; v < nv; v++)
                         acc[v] += dt * S[v];
+                /* internal energy (Sect. 2.4): e_new = e + alpha d1e + (1 - alpha) d2e, d1e from the
+                 * total energy (E - |m|^2 / (2 rho) of the updated cell), d2e from eq. pressure_fix
+                 * (acc above); alpha from e and e_k of the cell at time n (reading) */
+                if (c->dual_energy) {
+                    const double en = Q[(nv - 1) * nw + iw];
+                    double qn[5];
+                    for (int v = 0; v < 5; v++)
+                        qn[v] = Q[v * nw + iw];
+                    const double alpha = or_de_alpha(en, kinetic_energy(qn), c->de_eps);
+                    const double d1 = (acc[4] - kinetic_energy(acc)) - en;
+                    const double d2 = acc[nv - 1] - en;
+                    acc[nv - 1] = en + alpha * d1 + (1.0 - alpha) * d2;
+                }
                 if (nonphysical(&x, acc))
                     nonphys = 1;
                 long io = bidx(&bo, i, j, k);

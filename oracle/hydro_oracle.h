@@ -54,6 +54,9 @@ typedef struct {
     double g0[3];
     double G, Mc;
     const double *mlp;        /* OR_MLP_NPARAM weights, W1[32][4] b1 W2[32][32] b2 w3[32] b3 */
+    int dual_energy;          /* 1: the last field is the monitored internal energy e (Sect. 2.4,
+                                 eq. pressure_fix); needs HLLC */
+    double de_eps;            /* the criterion epsilon of the blend factor alpha (paper: 1e-6) */
 } or_config;
 
 /* Full step of interior U (layout [nvar][n3][n2][n1]) with time step dt into Unew.
@@ -74,6 +77,10 @@ void or_totals(const or_config *c, const double *U, double *tot);
 
 /* Enclosed mass M_enc(r_i) per radial shell (spherical wedge, Sect. 2.2 eq. internal_gravity). */
 int or_enclosed_mass(const or_config *c, const double *U, double *menc);
+
+/* Blend factor alpha of the internal-energy monitor (Sect. 2.4) for internal energy e and kinetic
+ * energy e_k (per unit volume) and the criterion eps. */
+double or_de_alpha(double e, double ek, double eps);
 
 /* Single-interface Riemann flux in direction d for conserved states qL, qR (nvar each). */
 void or_riemann_flux(int solver, int d, int nvar, double gamma, const double *qL, const double *qR,

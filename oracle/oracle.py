@@ -32,7 +32,7 @@ class OrConfig(C.Structure):
         ("faces", _DP * 3), ("nscalar", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double),
         ("riemann", C.c_int), ("limiter", C.c_int), ("bc", (C.c_int * 2) * 3),
         ("gravity", C.c_int), ("g0", C.c_double * 3), ("G", C.c_double), ("Mc", C.c_double),
-        ("mlp", _DP),
+        ("mlp", _DP), ("dual_energy", C.c_int), ("de_eps", C.c_double),
     ]
 
 
@@ -59,6 +59,8 @@ def lib(path: str = LIB_PATH):
         L.or_enclosed_mass.argtypes = [cp, _DP, _DP]
         L.or_riemann_flux.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _DP, _DP, _DP]
         L.or_riemann_flux.restype = None
+        L.or_de_alpha.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_de_alpha.restype = C.c_double
         L.or_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
         L.or_limiter.restype = C.c_double
         L.or_mlp_phi.argtypes = [_DP, _DP]
@@ -96,7 +98,8 @@ class Oracle:
         self.ndim = int(_get(prob, "ndim"))
         self.n = tuple(int(v) for v in _get(prob, "n"))
         self.nscalar = int(_get(prob, "nscalar"))
-        self.nvar = 5 + self.nscalar
+        dual = bool(getattr(prob, "dual_energy", False)) if not isinstance(prob, dict) else bool(prob.get("dual_energy", False))
+        self.nvar = 5 + self.nscalar + (1 if dual else 0)
         self._faces = [np.ascontiguousarray(f, dtype=np.float64) for f in _get(prob, "faces")]
         c = OrConfig()
         c.ndim = self.ndim
@@ -116,6 +119,8 @@ class Oracle:
         c.gravity = GRAVITY[_get(prob, "gravity")]
         c.G = float(_get(prob, "G"))
         c.Mc = float(_get(prob, "Mc"))
+        c.dual_energy = 1 if dual else 0
+        c.de_eps = float(getattr(prob, "de_eps", 1e-6)) if not isinstance(prob, dict) else float(prob.get("de_eps", 1e-6))
         self._mlp = None
         if mlp_weights is not None:
             self.set_mlp(mlp_weights)
@@ -285,4 +290,9 @@ def opcount_step(prob, U: np.ndarray, dt: float) -> dict:
     res["state"] = out
     res["status"] = st
     return res
+
+
+def de_alpha(e: float, ek: float, eps: float) -> float:
+    """Blend factor of the internal-energy monitor (Sect. 2.4)."""
+    return lib().or_de_alpha(float(e), float(ek), float(eps))
 

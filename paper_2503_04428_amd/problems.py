@@ -53,10 +53,12 @@ class Problem:
     t_end: float = 0.0
     nsteps: int = 0
     meta: dict = field(default_factory=dict)
+    dual_energy: bool = False     # last field = monitored internal energy e (Sect. 2.4)
+    de_eps: float = 1e-6          # criterion of the blend factor alpha
 
     @property
     def nvar(self) -> int:
-        return 5 + self.nscalar
+        return 5 + self.nscalar + (1 if self.dual_energy else 0)
 
     @property
     def ncells(self) -> int:
@@ -485,3 +487,49 @@ WORKLOADS = {
     "wedge": wedge3d,
     "learned": quadrant3d,
 }
+
+
+def with_internal_energy(prob: Problem, eps: float = 1e-6) -> Problem:
+    """The same problem with the internal-energy monitor of Sect. 2.4: one more field, initialised
+    to e = E - |m|^2 / (2 rho)."""
+    U = prob.U0
+    e = U[4] - 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0]
+    return prob.with_(name=prob.name + "+e", U0=np.concatenate([U, e[None]], axis=0), dual_energy=True,
+                      de_eps=float(eps), riemann="hllc")
+
+
+def boosted_sedov3d(n: int = 64, boost=(1.0, 0.5, 0.25), eps: float = 1e-6, **kw) -> Problem:
+    """Sedov blast in a medium moving at a uniform velocity (periodic box): the ambient gas is at
+    Mach ~300, so its internal energy is 1e-5 of its kinetic energy and the monitor's alpha
+    switches between its branches across the domain."""
+    p = sedov3d(n=n, **kw)
+    U = p.U0.copy()
+    rho = U[0]
+    for d in range(3):
+        U[1 + d] = U[1 + d] + rho * boost[d]
+    U[4] = U[4] + 0.5 * rho * float(np.dot(boost, boost))
+    q = p.with_(name="boosted_sedov", U0=U, bc=[["periodic"] * 2 for _ in range(3)],
+                faces=[ghost_faces(np.linspace(-1.0, 1.0, n + 1), p.ng, "periodic", "periodic") for _ in range(3)])
+    return with_internal_energy(q, eps)
+
+
+def acoustic_wave1d(n: int = 128, amp: float = 1e-3, ng: int = 2, limiter: str = "vanleer") -> Problem:
+    """Smooth isentropic right-going acoustic wave on a periodic unit interval (rho = 1, P = 1/gamma,
+    c = 1): a smooth flow where the internal-energy equation and the total-energy equation must
+    agree to the scheme's order."""
+    gamma = 1.4
+    f = np.linspace(0.0, 1.0, n + 1)
+    x = 0.5 * (f[:-1] + f[1:])
+    s = amp * np.sin(2.0 * np.pi * x)
+    rho = 1.0 + s
+    u = s  # c0 = 1, right-going: u = c0 drho / rho0
+    p = (1.0 / gamma) * rho ** gamma
+    U = np.zeros((5, 1, 1, n))
+    U[0, 0, 0] = rho
+    U[1, 0, 0] = rho * u
+    U[4, 0, 0] = p / (gamma - 1.0) + 0.5 * rho * u * u
+    return Problem(name="acoustic1d", ndim=1, geom="cart", n=(n, 1, 1), ng=ng,
+                   faces=[ghost_faces(f, ng, "periodic", "periodic"), np.array([0.0, 1.0]), np.array([0.0, 1.0])],
+                   nscalar=0, gamma=gamma, cfl=0.5, riemann="hllc", limiter=limiter,
+                   bc=[["periodic"] * 2, ["periodic"] * 2, ["periodic"] * 2], U0=U)
+
