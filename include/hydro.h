@@ -8,8 +8,8 @@
  * on Cartesian or spherical-wedge grids in 1D-3D (Sect. 3.1.1), including the spherical momentum
  * source terms of Sect. 3.1.2 (eq. source_terms_1 and its theta counterpart).
  *
- * Data layout.  A state is nvar = 5 + nscalar fields, structure of arrays, x fastest:
- *   U[v][k][j][i], v in (rho, rho u1, rho u2, rho u3, E, rho f_1 .. rho f_nscalar),
+ * Data layout.  A state is nvar = 5 + nscalar (+ 1 with dual_energy) fields, structure of arrays,
+ * x fastest: U[v][k][j][i], v in (rho, rho u1, rho u2, rho u3, E, rho f_1 .. rho f_nscalar[, e]),
  *   i < n[0], j < n[1], k < n[2]; interior cells only (ghost cells are never stored).
  * In spherical geometry axis 0 is r, axis 1 theta, axis 2 phi, and (u1, u2, u3) = (u_r, u_theta,
  * u_phi).  All three momentum components are carried in every dimension.
@@ -78,6 +78,11 @@ typedef struct {
                                mass of the wedge, scaled to the full sphere (eq. internal_gravity) */
     double g0[3];
     double G, Mc;
+    int dual_energy;        /* 1: the last field is the monitored internal energy e per unit volume
+                               (Sect. 2.4: eq. pressure_fix with -P div(u), and the alpha blend of
+                               the total- and internal-energy updates); needs FP64, HLLC, a
+                               limiter other than the learned one and nscalar <= 3.  0: off */
+    double de_eps;          /* the blend criterion epsilon (the paper uses 1e-6), >= 0 */
 } hx_config;
 
 /* Device bytes the caller must provide to hx_create for this configuration, or 0 if the

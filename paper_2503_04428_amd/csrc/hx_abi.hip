@@ -78,7 +78,7 @@ struct Layout {
     int nchunk, nred;
 };
 
-int nvar_of(const hx_config* c) { return 5 + c->nscalar; }
+int nvar_of(const hx_config* c) { return 5 + c->nscalar + (c->dual_energy ? 1 : 0); }
 
 long long ncells_of(const hx_config* c) { return (long long)c->n[0] * c->n[1] * c->n[2]; }
 
@@ -108,6 +108,20 @@ hx_status validate(const hx_config* c)
     }
     if (c->riemann != HX_RIEMANN_HLL && c->riemann != HX_RIEMANN_HLLC)
         return fail(HX_EINVAL, "unknown Riemann solver %d", c->riemann);
+    if (c->dual_energy != 0 && c->dual_energy != 1)
+        return fail(HX_EINVAL, "dual_energy must be 0 or 1 (got %d)", c->dual_energy);
+    if (c->dual_energy) {
+        if (c->precision != HX_PRECISION_FP64)
+            return fail(HX_EINVAL, "the internal-energy monitor is built for the FP64 form");
+        if (c->riemann != HX_RIEMANN_HLLC)
+            return fail(HX_EINVAL, "the internal-energy monitor needs HLLC (its interface velocity)");
+        if (c->limiter == HX_LIMITER_MLP)
+            return fail(HX_EINVAL, "the internal-energy monitor is not built with the learned limiter");
+        if (c->nscalar > 3)
+            return fail(HX_EINVAL, "with the internal-energy monitor at most 3 passive scalars");
+        if (!(c->de_eps >= 0.0))
+            return fail(HX_EINVAL, "de_eps must be >= 0");
+    }
     if (c->precision != HX_PRECISION_FP64 && c->precision != HX_PRECISION_FP32)
         return fail(HX_EINVAL, "unknown precision %d", c->precision);
     if (!(c->gamma > 1.0) || !(c->cfl > 0.0))
@@ -402,11 +416,14 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     p.flag = at<int>(x, x->L.flag);
     p.dtpart = at<double>(x, x->L.dtpart);
     p.mlp = at<float>(x, x->L.mlp);
+    p.de_eps = c.de_eps;
     const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC;
     if (c.limiter == HX_LIMITER_MLP && !x->have_mlp)
         return fail(HX_ESTATE, "the learned limiter needs hx_set_mlp before stepping");
     // the instantiation for this configuration; with occ, only its workgroups per compute unit
     auto sweep = [&](int* occ) -> hipError_t {
+        if (c.dual_energy)
+            return hx::launch_sweep_fp64_de(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (c.limiter == HX_LIMITER_MLP)
             return hx::launch_sweep_fp32_mlp(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (x->fp32)

@@ -38,12 +38,14 @@ struct Gas {
 
 // ---------------------------------------------------------------- EoS
 
-// primitives from conserved
-template <typename R, int NV>
+// primitives from conserved.  DE: the last field is the monitored internal energy e, which is
+// its own primitive (per unit volume, like the pressure); the passive scalars before it are
+// carried per unit mass.
+template <typename R, int NV, bool DE>
 struct PrimImpl;
 
-template <int NV>
-struct PrimImpl<double, NV> {
+template <int NV, bool DE>
+struct PrimImpl<double, NV, DE> {
     static __device__ __forceinline__ double run(const Gas<double>& g, const double* q, double* w)
     {
         double rho = q[0];
@@ -56,14 +58,16 @@ struct PrimImpl<double, NV> {
         w[3] = u3;
         w[4] = g.gm1 * (q[4] - ke);
 #pragma unroll
-        for (int v = 5; v < NV; v++)
+        for (int v = 5; v < NV - DE; v++)
             w[v] = q[v] * inv;
+        if (DE)
+            w[NV - 1] = q[NV - 1];
         return inv;
     }
 };
 
-template <int NV>
-struct PrimImpl<float, NV> {
+template <int NV, bool DE>
+struct PrimImpl<float, NV, DE> {
     // FP32 bulk, FP64 island for the internal energy: 1/rho from the hardware reciprocal refined
     // by one FP64 Newton step, then e = E - |m|^2/(2 rho) in FP64.
     static __device__ __forceinline__ float run(const Gas<float>& g, const float* q, float* w)
@@ -81,17 +85,41 @@ struct PrimImpl<float, NV> {
         w[3] = q[3] * inv;
         w[4] = (float)((double)g.gm1 * ((double)q[4] - ke));
 #pragma unroll
-        for (int v = 5; v < NV; v++)
+        for (int v = 5; v < NV - DE; v++)
             w[v] = q[v] * inv;
+        if (DE)
+            w[NV - 1] = q[NV - 1];
         return inv;
     }
 };
 
 // returns the reciprocal density used for the velocities
-template <typename R, int NV>
+template <typename R, int NV, bool DE = false>
 __device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w)
 {
-    return PrimImpl<R, NV>::run(g, q, w);
+    return PrimImpl<R, NV, DE>::run(g, q, w);
+}
+
+// kinetic energy |m|^2 / (2 rho) of a conserved state
+template <typename R>
+__device__ __forceinline__ R kinetic_energy(const R* q)
+{
+    return R(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+}
+
+// blend factor of the internal-energy monitor (Sect. 2.4): 1 for e >= eps e_k,
+// (e / (eps e_k))^2 down to eps e_k / 10, 0 below
+template <typename R>
+__device__ __forceinline__ R de_alpha(R e, R ek, R eps)
+{
+    const R t = eps * ek;
+    if (e >= t)
+        return R(1);
+    if (e > t / R(10)) {
+        const R r = e / t;
+        return r * r;
+    }
+    return R(0);
 }
 
 // rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division)
@@ -102,7 +130,7 @@ __device__ __forceinline__ bool positive_state(const R* q)
     return q[0] > R(0) && R(2) * q[0] * q[4] - m2 > R(0);
 }
 
-template <typename R, int NV>
+template <typename R, int NV, bool DE = false>
 __device__ __forceinline__ void to_cons(const Gas<R>& g, const R* w, R* q)
 {
     R rho = w[0];
@@ -112,12 +140,14 @@ __device__ __forceinline__ void to_cons(const Gas<R>& g, const R* w, R* q)
     q[3] = rho * w[3];
     q[4] = w[4] * g.inv_gm1 + R(0.5) * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
 #pragma unroll
-    for (int v = 5; v < NV; v++)
+    for (int v = 5; v < NV - DE; v++)
         q[v] = rho * w[v];
+    if (DE)
+        q[NV - 1] = w[NV - 1];
 }
 
 // physical flux along axis D from primitives w and conserved q of the same state
-template <typename R, int NV, int D>
+template <typename R, int NV, int D, bool DE = false>
 __device__ __forceinline__ void phys_flux(const R* w, const R* q, R* f)
 {
     R un = w[1 + D];
@@ -129,18 +159,23 @@ __device__ __forceinline__ void phys_flux(const R* w, const R* q, R* f)
     f[1 + D] = f[1 + D] + w[4];
     f[4] = un * (q[4] + w[4]);
 #pragma unroll
-    for (int v = 5; v < NV; v++)
+    for (int v = 5; v < NV - DE; v++)
         f[v] = mn * w[v];
+    if (DE)
+        f[NV - 1] = un * w[NV - 1];  // u e
 }
 
 // HLL / HLLC with Davis wave speeds (Sect. 3.2; textbook solvers the paper cites)
-template <typename R, int NV, int D>
-__device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL, const R* qR, R* F)
+// uf (if not null) receives the interface velocity: the contact speed S* in the HLLC star
+// region, else the normal velocity of the upwind side (HLL leaves it unset).
+template <typename R, int NV, int D, bool DE = false>
+__device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL, const R* qR, R* F,
+                                        R* uf = nullptr)
 {
     using N = Num<R>;
     R wL[NV], wR[NV];
-    const R iL = to_prim<R, NV>(g, qL, wL);
-    const R iR = to_prim<R, NV>(g, qR, wR);
+    const R iL = to_prim<R, NV, DE>(g, qL, wL);
+    const R iR = to_prim<R, NV, DE>(g, qR, wR);
     R rL = wL[0], rR = wR[0];
     R uL = wL[1 + D], uR = wR[1 + D];
     R pL = wL[4], pR = wR[4];
@@ -150,8 +185,8 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
     R SR = fmax(uL + cL, uR + cR);
     if (solver == HX_HLL) {
         R fL[NV], fR[NV];
-        phys_flux<R, NV, D>(wL, qL, fL);
-        phys_flux<R, NV, D>(wR, qR, fR);
+        phys_flux<R, NV, D, DE>(wL, qL, fL);
+        phys_flux<R, NV, D, DE>(wR, qR, fR);
         if (SL >= R(0)) {
 #pragma unroll
             for (int v = 0; v < NV; v++)
@@ -187,7 +222,9 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
         qs[v] = left ? qL[v] : qR[v];
         ws[v] = left ? wL[v] : wR[v];
     }
-    phys_flux<R, NV, D>(ws, qs, fs);
+    phys_flux<R, NV, D, DE>(ws, qs, fs);
+    if (uf)
+        *uf = star ? Ss : (left ? uL : uR);
     if (!star) {
 #pragma unroll
         for (int v = 0; v < NV; v++)
@@ -204,8 +241,10 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
     us[1 + D] = fac * Ss;
     us[4] = fac * (qs[4] * iv + (Ss - un) * (Ss + N::div(ws[4], m)));
 #pragma unroll
-    for (int v = 5; v < NV; v++)
+    for (int v = 5; v < NV - DE; v++)
         us[v] = fac * ws[v];
+    if (DE)
+        us[NV - 1] = fac * (ws[NV - 1] * iv);  // rho* e / rho of the side
 #pragma unroll
     for (int v = 0; v < NV; v++)
         F[v] = fs[v] + S * (us[v] - qs[v]);

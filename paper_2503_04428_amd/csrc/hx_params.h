@@ -63,6 +63,7 @@ struct SweepParams {
     double* dtpart;      // per-workgroup maximum CFL rate of U^{n+1}
     int kz;              // z planes per block (3D)
     const float* mlp;    // learned limiter weights (FP32 master copy)
+    double de_eps;       // criterion of the internal-energy monitor's blend factor
 };
 
 }  // namespace hx

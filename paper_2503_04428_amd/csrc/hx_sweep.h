@@ -35,12 +35,13 @@ namespace hx {
 #ifndef HX_RESLOPE_FP64
 #define HX_RESLOPE_FP64 0
 #endif
-template <typename R, int NV, int NDIM>
+template <typename R, int NV, int NDIM, int SPEC>
 struct MinWaves {
 #ifdef HX_MINW_FP64
     static constexpr int fp64 = HX_MINW_FP64;
 #else
-    static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV ? 2 : 1;
+    // (the internal-energy monitor's extra state spills at two waves even with 6 fields)
+    static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV && SPEC != 3 ? 2 : 1;
 #endif
     static constexpr int value = sizeof(R) == 8 ? fp64 : HX_MINW_FP32;
 };
@@ -136,9 +137,11 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 
 // SPEC = 1 compiles the common HLLC + van Leer case with both choices fixed; SPEC = 2 the learned
 // limiter with HLLC (slope stencil of half-width 2, BF16 matrix-core network); SPEC = 0 reads the
-// limiter and the Riemann solver from the parameters.
+// limiter and the Riemann solver from the parameters; SPEC = 3 adds the internal-energy monitor
+// (Sect. 2.4: the last field is e, with eq. pressure_fix and the alpha blend; HLLC, limiter from
+// the parameters).
 template <typename R, int NV, int NDIM, int GEOM, int SPEC>
-__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM>::value))
+__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, SPEC>::value))
     sweep_kernel(const SweepParams p)
 {
     using N = Num<R>;
@@ -146,6 +149,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     constexpr int BY = Tile<NDIM>::BY;
     constexpr int NT = BX * BY;
     constexpr bool MLP = SPEC == 2;
+    constexpr bool DE = SPEC == 3;  // internal-energy monitor: the last field is e (FP64, HLLC)
     constexpr int S = MLP ? 2 : 1;  // half-width of the slope stencil
     constexpr int RX = BX + 2 * S;
     constexpr int RY = NDIM >= 2 ? BY + 2 * S : 1;
@@ -158,6 +162,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     __shared__ R sW[NSLOT][NV][RY * RX];  // primitives of a plane incl. a 2-cell ring
     __shared__ R sFy[NV][NYB];            // +y half-step state of every predictor cell
     __shared__ R sGy[NV][NYB];            // y flux through the lower face of every cell
+    __shared__ R sGu[DE ? NYB : 1];       // and its interface velocity (internal-energy monitor)
     __shared__ double sRed[NWAVE];
     // learned limiter: per-wave queue of the stencils that need the network, and its outputs
     __shared__ unsigned long long sQ[MLP ? NWAVE : 1][MLP ? 2 * 64 * NV : 1];
@@ -318,7 +323,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             q[2] = -q[2];
         if (fk)
             q[3] = -q[3];
-        to_prim<R, NV>(gas, q, w);
+        to_prim<R, NV, DE>(gas, q, w);
         const bool kin = NDIM < 3 || (k >= 0 && k < n2);
         if (kin && interior && bad_state<R, NV>(q, w))
             p.flag[0] = 1;
@@ -334,7 +339,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             if (fk)
                 q[3] = -q[3];
             R w[NV];
-            to_prim<R, NV>(gas, q, w);
+            to_prim<R, NV, DE>(gas, q, w);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 sW[s][v][ring_lds] = w[v];
@@ -461,6 +466,16 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     R uzp[NV];     // +z half-step state of plane k-1
     double sg[5];  // gravity source of plane k-1 (components 1..4)
     double sph_t[6];  // spherical partial sources of plane k-1: Trt, Trp, Tt, Xt, grg, gtg
+    // internal-energy monitor, plane k-1: P of its half-step e, its e^n and blend factor, and the
+    // interface velocity of its lower z face
+    R pe_prev = R(0), en_prev = R(0), alpha_prev = R(0), ufzlo = R(0);
+    // e_new = e^n + alpha d1e + (1 - alpha) d2e: d1e from the updated total energy, d2e from the
+    // internal-energy equation (the last field of the updated state a)
+    auto de_blend = [&](R* a, R en, R alpha) {
+        const R d1 = (a[4] - kinetic_energy<R>(a)) - en;
+        const R d2 = a[NV - 1] - en;
+        a[NV - 1] = en + alpha * d1 + (R(1) - alpha) * d2;
+    };
     double w2prev = 0.0;  // z width of plane k-1 (loaded for its predictor; the kernel's own stores
                           // would force the finish of the plane to load it again from memory)
 #pragma unroll
@@ -589,13 +604,16 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 wm[v] = wcur[v] - dlt[0][v];
                 wp[v] = wcur[v] + dlt[0][v];
             }
-            to_cons<R, NV>(gas, wm, um);
-            to_cons<R, NV>(gas, wp, up);
-            phys_flux<R, NV, 0>(wm, um, fm);
-            phys_flux<R, NV, 0>(wp, up, fp);
+            to_cons<R, NV, DE>(gas, wm, um);
+            to_cons<R, NV, DE>(gas, wp, up);
+            phys_flux<R, NV, 0, DE>(wm, um, fm);
+            phys_flux<R, NV, 0, DE>(wp, up, fp);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 du[v] += lamx * (fm[v] - fp[v]);
+            // internal energy: -(dt/2) P div(u) with the reconstructed face velocities, P of e^n
+            if constexpr (DE)
+                du[NV - 1] += lamx * ((gas.gm1 * qcur[NV - 1]) * (wm[1 + 0] - wp[1 + 0]));
         }
         if (NDIM >= 2) {
             if constexpr (!MLP)
@@ -606,13 +624,16 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 wm[v] = wcur[v] - dlt[1][v];
                 wp[v] = wcur[v] + dlt[1][v];
             }
-            to_cons<R, NV>(gas, wm, um);
-            to_cons<R, NV>(gas, wp, up);
-            phys_flux<R, NV, 1>(wm, um, fm);
-            phys_flux<R, NV, 1>(wp, up, fp);
+            to_cons<R, NV, DE>(gas, wm, um);
+            to_cons<R, NV, DE>(gas, wp, up);
+            phys_flux<R, NV, 1, DE>(wm, um, fm);
+            phys_flux<R, NV, 1, DE>(wp, up, fp);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 du[v] += lamy * (fm[v] - fp[v]);
+            // internal energy: -(dt/2) P div(u) with the reconstructed face velocities, P of e^n
+            if constexpr (DE)
+                du[NV - 1] += lamy * ((gas.gm1 * qcur[NV - 1]) * (wm[1 + 1] - wp[1 + 1]));
         }
         if (NDIM == 3) {
             commit_own(k + S, qz[S], wz[2 * S]);
@@ -628,13 +649,16 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 wm[v] = wcur[v] - dlt[2][v];
                 wp[v] = wcur[v] + dlt[2][v];
             }
-            to_cons<R, NV>(gas, wm, um);
-            to_cons<R, NV>(gas, wp, up);
-            phys_flux<R, NV, 2>(wm, um, fm);
-            phys_flux<R, NV, 2>(wp, up, fp);
+            to_cons<R, NV, DE>(gas, wm, um);
+            to_cons<R, NV, DE>(gas, wp, up);
+            phys_flux<R, NV, 2, DE>(wm, um, fm);
+            phys_flux<R, NV, 2, DE>(wp, up, fp);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 du[v] += lamz * (fm[v] - fp[v]);
+            // internal energy: -(dt/2) P div(u) with the reconstructed face velocities, P of e^n
+            if constexpr (DE)
+                du[NV - 1] += lamz * ((gas.gm1 * qcur[NV - 1]) * (wm[1 + 2] - wp[1 + 2]));
         }
         if (p.gravity != HX_GRAV_NONE) {
             // (dt/2) S(U^n) with S = (0, rho g, m.g, 0)
@@ -672,7 +696,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
-                to_cons<R, NV>(gas, ws, qs);
+                to_cons<R, NV, DE>(gas, ws, qs);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     qs[v] += du[v];
@@ -719,7 +743,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     const R dv = RESLOPE && bad ? R(0) : dd[v];
                     ws[v] = side ? wcur[v] + dv : wcur[v] - dv;
                 }
-                to_cons<R, NV>(gas, ws, out);
+                to_cons<R, NV, DE>(gas, ws, out);
                 if (!bad) {
 #pragma unroll
                     for (int v = 0; v < NV; v++)
@@ -730,7 +754,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
-            to_cons<R, NV>(gas, ws, out);
+            to_cons<R, NV, DE>(gas, ws, out);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 out[v] += du[v];
@@ -738,18 +762,25 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ws[v] = side ? wcur[v] + R(0) : wcur[v] - R(0);
-                to_cons<R, NV>(gas, ws, out);
+                to_cons<R, NV, DE>(gas, ws, out);
             }
         };
         // sources of the cell half-step state uh = U^n + du (U^n in the fallback): gravity
         // (0, rho g, m.g) now; the spherical terms keep uh for the update
         R uh[GEOM == HX_SPH ? NV : 1];
         double Sg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        // internal-energy monitor: P of the half-step e (for -P div(u)), e^n and the blend factor
+        R pek = R(0), enk = R(0), alphak = R(0);
         {
             R u[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 u[v] = bad ? qcur[v] : qcur[v] + du[v];
+            if constexpr (DE) {
+                pek = gas.gm1 * u[NV - 1];
+                enk = qcur[NV - 1];
+                alphak = de_alpha<R>(enk, kinetic_energy<R>(qcur), N::from_d(p.de_eps));
+            }
             if (p.gravity != HX_GRAV_NONE) {
                 Sg[1] = (double)u[0] * g[0];
                 Sg[2] = (double)u[0] * g[1];
@@ -770,12 +801,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         const bool plane_live = NDIM < 3 || (k >= k0 && k < k1);
         if (NDIM == 3) {
             // z: the +z state of plane k-1 is held by the thread; plane k's replaces it
-            R Fz[NV];
+            R Fz[NV], ufz = R(0);
             {
                 R dd[NV], qmz[NV];
                 axis_dl(2, dd);
                 face_state(dd, 0, qmz);
-                riemann<R, NV, 2>(solver, gas, uzp, qmz, Fz);
+                riemann<R, NV, 2, DE>(solver, gas, uzp, qmz, Fz, DE ? &ufz : nullptr);
                 face_state(dd, 1, uzp);
             }
             // finish plane k-1 with its z terms and sources, then store it
@@ -786,6 +817,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += mu * (fzlo[v] - Fz[v]);
+                    if constexpr (DE)
+                        acc[NV - 1] += mu * (pe_prev * (ufzlo - ufz));
                 } else {
                     const double dph = w2prev;
                     const double dV = p.geo.vr[ii] * p.geo.ct[jj] * dph;
@@ -794,6 +827,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += kv * (fzlo[v] * dS - Fz[v] * dS);
+                    if constexpr (DE)
+                        acc[NV - 1] += kv * (pe_prev * (ufzlo * dS - ufz * dS));
                 }
                 if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
                     double S[5] = {0.0, sg[1], sg[2], sg[3], sg[4]};
@@ -807,6 +842,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     for (int v = 1; v < 5; v++)
                         acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
                 }
+                if constexpr (DE)
+                    de_blend(acc, en_prev, alpha_prev);
                 const long long off = ((long long)kp * n1 + jj) * n0 + ii;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -820,8 +857,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 fzlo[v] = Fz[v];
+            if constexpr (DE)
+                ufzlo = ufz;
         }
-        R Fx[NV], Fxr[NV];
+        R Fx[NV], Fxr[NV], ufx = R(0), ufxr = R(0);
         {
             // x: the +x state of the left neighbour arrives by a row shift
             R qmx[NV], L[NV];
@@ -839,10 +878,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 for (int v = 0; v < NV; v++)
                     L[v] = qmx[v];
             }
-            riemann<R, NV, 0>(solver, gas, L, qmx, Fx);
+            riemann<R, NV, 0, DE>(solver, gas, L, qmx, Fx, DE ? &ufx : nullptr);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 Fxr[v] = from_right<BX>(Fx[v]);
+            if constexpr (DE)
+                ufxr = from_right<BX>(ufx);
         }
         // x terms of plane k (and the spherical x parts of its sources)
         const bool upd = interior && plane_live;
@@ -857,6 +898,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     acc[v] += mu * (Fx[v] - Fxr[v]);
+                if constexpr (DE)
+                    acc[NV - 1] += mu * (pek * (ufx - ufxr));
             } else {
                 const int kin = NDIM == 3 ? k : 0;
                 dph = NDIM == 3 ? w2k : p.geo.w[2][0];
@@ -871,6 +914,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     acc[v] += kv * (Fx[v] * sm - Fxr[v] * sp);
+                if constexpr (DE)
+                    acc[NV - 1] += kv * (pek * (ufx * sm - ufxr * sp));
                 cr = (rp - rm) / ((rp + rm) * dV);
                 Trt = -cr * ((double)Fxr[2] * dSrp + (double)Fx[2] * dSrm);
                 Trp = -cr * ((double)Fxr[3] * dSrp + (double)Fx[3] * dSrm);
@@ -878,7 +923,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         }
 
         // y: +y states through LDS, then the fluxes of the upper faces through LDS
-        R Fy[NV], Fyu[NV];
+        R Fy[NV], Fyu[NV], ufy = R(0), ufyu = R(0);
         {
             R qmy[NV];
             if (NDIM >= 2) {
@@ -896,16 +941,20 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     L[v] = ty > 0 ? sFy[v][tid - BX] : qmy[v];
-                riemann<R, NV, 1>(solver, gas, L, qmy, Fy);
+                riemann<R, NV, 1, DE>(solver, gas, L, qmy, Fy, DE ? &ufy : nullptr);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     sGy[v][tid] = Fy[v];
+                if constexpr (DE)
+                    sGu[tid] = ufy;
             }
             __syncthreads();
             if (NDIM >= 2) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     Fyu[v] = ty < BY - 1 ? sGy[v][tid + BX] : Fy[v];
+                if constexpr (DE)
+                    ufyu = ty < BY - 1 ? sGu[tid + BX] : ufy;
             }
         }
 
@@ -917,6 +966,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += muy * (Fy[v] - Fyu[v]);
+                    if constexpr (DE)
+                        acc[NV - 1] += muy * (pek * (ufy - ufyu));
                 } else {
                     const double kvd = dtd / dV;
                     const R kv = N::from_d(kvd);
@@ -926,6 +977,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += kv * (Fy[v] * tm - Fyu[v] * tp);
+                    if constexpr (DE)
+                        acc[NV - 1] += kv * (pek * (ufy * tm - ufyu * tp));
                 }
             }
             // sources of plane k (finished now in 1D/2D, after the z terms in 3D)
@@ -935,7 +988,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 double pu = 0.0;
                 if (NDIM < 3) {
                     R wu[NV];
-                    to_prim<R, NV>(gas, uh, wu);
+                    to_prim<R, NV, DE>(gas, uh, wu);
                     pu = (double)wu[4];
                 }
                 double Xt, Tt = 0.0, gtg = 0.0;
@@ -972,6 +1025,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     for (int v = 1; v < 5; v++)
                         acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
                 }
+                if constexpr (DE)
+                    de_blend(acc, enk, alphak);
                 const long long off = ((long long)jj * n0) + ii;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -985,6 +1040,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         }
         if (NDIM == 3) {
             w2prev = w2k;
+            if constexpr (DE) {
+                pe_prev = pek;
+                en_prev = enk;
+                alpha_prev = alphak;
+            }
 #pragma unroll
             for (int v = 0; v < NV; v++) {
 #pragma unroll

@@ -34,7 +34,7 @@ class HxConfig(C.Structure):
         ("faces", _DP * 3), ("nscalar", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double),
         ("riemann", C.c_int), ("limiter", C.c_int), ("precision", C.c_int),
         ("bc", (C.c_int * 2) * 3), ("gravity", C.c_int), ("g0", C.c_double * 3),
-        ("G", C.c_double), ("Mc", C.c_double),
+        ("G", C.c_double), ("Mc", C.c_double), ("dual_energy", C.c_int), ("de_eps", C.c_double),
     ]
 
 
@@ -104,6 +104,10 @@ def _get(p, k):
     return p[k] if isinstance(p, dict) else getattr(p, k)
 
 
+def _opt(p, k, default):
+    return p.get(k, default) if isinstance(p, dict) else getattr(p, k, default)
+
+
 def make_config(prob, precision: str | None = None):
     """hx_config for a problem description (see problems.Problem); returns (config, keepalive)."""
     c = HxConfig()
@@ -127,6 +131,8 @@ def make_config(prob, precision: str | None = None):
     c.gravity = GRAVITY[_get(prob, "gravity")]
     c.G = float(_get(prob, "G"))
     c.Mc = float(_get(prob, "Mc"))
+    c.dual_energy = 1 if _opt(prob, "dual_energy", False) else 0
+    c.de_eps = float(_opt(prob, "de_eps", 1e-6))
     return c, faces
 
 
@@ -153,7 +159,7 @@ class Solver:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.cfg, self._faces = make_config(prob, precision)
-        self.nvar = 5 + int(_get(prob, "nscalar"))
+        self.nvar = 5 + int(_get(prob, "nscalar")) + (1 if _opt(prob, "dual_energy", False) else 0)
         n = [int(v) for v in _get(prob, "n")]
         self.shape = (self.nvar, n[2], n[1], n[0])
         nbytes = self.L.hx_workspace_bytes(C.byref(self.cfg))
