@@ -194,8 +194,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the Sedov cube")
-    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod"],
-                    help="sedov (default, the headline line); rt, wedge, sod measure the other workloads")
+    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod", "boosted"],
+                    help="sedov (default, the headline line); rt, wedge, sod, boosted (Sedov in a moving "
+                         "medium with the internal-energy monitor, FP64) measure the other workloads")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
@@ -226,6 +227,11 @@ def main():
     if args.workload == "sedov":
         prob = problems.sedov3d(n=args.n)
         wl = f"sedov3d-{args.n}^3 (5 conserved + 2 passive scalars, HLLC, van Leer, CFL 0.5)"
+    elif args.workload == "boosted":
+        prob = problems.boosted_sedov3d(n=args.n, eps=1e-3)
+        wl = (f"boosted-sedov3d-{args.n}^3 with the internal-energy monitor (periodic, 8 fields, HLLC, "
+              f"van Leer, eps 1e-3)")
+        args.forms = "fp64"
     elif args.workload == "rt":
         prob = problems.rt3d()
         wl = "rt3d-128x128x512 (uniform gravity, 1 scalar, periodic x/y, reflective z, HLLC, van Leer)"
