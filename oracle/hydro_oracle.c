@@ -40,6 +40,9 @@ typedef struct {
     double gm1;       /* gamma - 1 */
     double inv_gm1;   /* 1 / (gamma - 1) */
     int de;           /* 1: the last field is the monitored internal energy e */
+    double gamma;
+    int eos;          /* OR_EOS_GAS or OR_EOS_GAS_RAD */
+    double R, arad;   /* gas + radiation: specific gas constant k_b/(mu m_u), radiation constant */
     double *gr;       /* radial gravity per interior shell (point / monopole), or NULL */
 } Ctx;
 
@@ -193,9 +196,46 @@ static void gravity_at(const Ctx *x, int i, int j, int k, double g[3])
 
 /* ------------------------------------------------------------------ EoS and fluxes */
 
-/* primitives (rho, u1, u2, u3, P, f...) from conserved (Sect. 2.1, eq. eos_gas); the reciprocal
+/* ---- gas + radiation EoS (Sect. 2.3, eqs. eos_gp_rad_ein, eos_gp_rad): e = rho R T/(gamma-1) +
+ * a T^4 and P = rho R T + a T^4 / 3.  The temperature follows from e (or, for primitive ->
+ * conserved, from P) by Newton's method.  Both residuals are convex and increasing in T, so Newton
+ * started from the smaller of the gas-only and the radiation-only temperatures (each an upper
+ * bound of the root) decreases monotonically to it; a fixed number of steps (the paper: about
+ * ten) keeps the computation identical on every input (reading). */
+#define EOS_NEWTON_STEPS 10
+
+static double t4(double T) { return (T * T) * (T * T); }
+
+static double temp_from_e(const Ctx *x, double rho, double e)
+{
+    const double cg = (rho * x->R) / x->gm1;
+    const double tg = e / cg, tr = sqrt(sqrt(e / x->arad));
+    double T = tg < tr ? tg : tr;
+    for (int it = 0; it < EOS_NEWTON_STEPS; it++) {
+        const double f = cg * T + x->arad * t4(T) - e;
+        const double fp = cg + 4.0 * x->arad * ((T * T) * T);
+        T = T - f / fp;
+    }
+    return T;
+}
+
+static double temp_from_p(const Ctx *x, double rho, double P)
+{
+    const double cg = rho * x->R;
+    const double tg = P / cg, tr = sqrt(sqrt((3.0 * P) / x->arad));
+    double T = tg < tr ? tg : tr;
+    for (int it = 0; it < EOS_NEWTON_STEPS; it++) {
+        const double f = cg * T + (x->arad * t4(T)) / 3.0 - P;
+        const double fp = cg + (4.0 * x->arad * ((T * T) * T)) / 3.0;
+        T = T - f / fp;
+    }
+    return T;
+}
+
+/* primitives (rho, u1, u2, u3, P, f...) from conserved (Sect. 2.1; P from eq. eos_gas, or from
+ * the temperature of the gas + radiation EoS, returned in *T if T is not NULL); the reciprocal
  * density is returned for the sound speed and the HLLC star energy */
-static double prim_inv(const Ctx *x, const double *q, double *w)
+static double prim_inv_t(const Ctx *x, const double *q, double *w, double *T)
 {
     double rho = q[0];
     double inv = 1.0 / rho;
@@ -205,7 +245,14 @@ static double prim_inv(const Ctx *x, const double *q, double *w)
     w[1] = u1;
     w[2] = u2;
     w[3] = u3;
-    w[4] = x->gm1 * (q[4] - ke);
+    if (x->eos == OR_EOS_GAS_RAD) {
+        const double Tt = temp_from_e(x, rho, q[4] - ke);
+        w[4] = (rho * x->R) * Tt + (x->arad * t4(Tt)) / 3.0;
+        if (T)
+            *T = Tt;
+    } else {
+        w[4] = x->gm1 * (q[4] - ke);
+    }
     for (int v = 5; v < x->nvar - x->de; v++)
         w[v] = q[v] * inv;
     /* the internal energy is reconstructed per unit volume, like the pressure, so that it stays
@@ -215,7 +262,23 @@ static double prim_inv(const Ctx *x, const double *q, double *w)
     return inv;
 }
 
+static double prim_inv(const Ctx *x, const double *q, double *w) { return prim_inv_t(x, q, w, NULL); }
+
 static void prim(const Ctx *x, const double *q, double *w) { (void)prim_inv(x, q, w); }
+
+/* sound speed of primitives w (reciprocal density inv, temperature T for the gas + radiation
+ * EoS): eq. eos_gas, or eq. cs_gp_rad with alpha = P_r / P_g */
+static double sound_speed(const Ctx *x, const double *w, double inv, double T)
+{
+    if (x->eos != OR_EOS_GAS_RAD)
+        return sqrt(x->gamma * w[4] * inv);
+    const double pg = (w[0] * x->R) * T;
+    const double pr = (x->arad * t4(T)) / 3.0;
+    const double al = pr / pg;
+    const double num = x->gamma / x->gm1 + 20.0 * al + 16.0 * (al * al);
+    const double den = 1.0 / x->gm1 + 12.0 * al;
+    return sqrt((num / den) * (pg * inv));
+}
 
 static void cons(const Ctx *x, const double *w, double *q)
 {
@@ -224,7 +287,13 @@ static void cons(const Ctx *x, const double *w, double *q)
     q[1] = rho * w[1];
     q[2] = rho * w[2];
     q[3] = rho * w[3];
-    q[4] = w[4] * x->inv_gm1 + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+    if (x->eos == OR_EOS_GAS_RAD) {
+        const double T = temp_from_p(x, rho, w[4]);
+        const double e = ((rho * x->R) * T) / x->gm1 + x->arad * t4(T);
+        q[4] = e + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+    } else {
+        q[4] = w[4] * x->inv_gm1 + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+    }
     for (int v = 5; v < x->nvar - x->de; v++)
         q[v] = rho * w[v];
     if (x->de)
@@ -259,26 +328,22 @@ static void phys_flux(int nvar, int de, int d, const double *w, const double *q,
  * Toro's textbook, which the paper cites for them). */
 /* uf (if not NULL) receives the velocity of the interface: the upwind side's normal velocity
  * outside the star region, the contact speed S* inside it (HLLC; HLL leaves it unset). */
-static void riemann(int solver, int d, int nvar, int de, double gamma, double gm1, const double *qL,
-                    const double *qR, double *F, double *uf)
+static void riemann(int solver, int d, const Ctx *x, const double *qL, const double *qR, double *F,
+                    double *uf)
 {
-    Ctx x;
-    memset(&x, 0, sizeof x);
-    x.nvar = nvar;
-    x.de = de;
-    x.gm1 = gm1;
-    x.inv_gm1 = 1.0 / gm1;
+    const int nvar = x->nvar, de = x->de;
     double wL[MAXV], wR[MAXV], fL[MAXV], fR[MAXV];
-    double iL = prim_inv(&x, qL, wL);
-    double iR = prim_inv(&x, qR, wR);
+    double TL = 0.0, TR = 0.0;
+    double iL = prim_inv_t(x, qL, wL, &TL);
+    double iR = prim_inv_t(x, qR, wR, &TR);
     phys_flux(nvar, de, d, wL, qL, fL);
     phys_flux(nvar, de, d, wR, qR, fR);
     double rL = wL[0], rR = wR[0];
     double uL = wL[1 + d], uR = wR[1 + d];
     double pL = wL[4], pR = wR[4];
-    /* c_s = sqrt(gamma P / rho) (eq. eos_gas), with the reciprocal density formed above */
-    double cL = sqrt(gamma * pL * iL);
-    double cR = sqrt(gamma * pR * iR);
+    /* sound speeds with the reciprocal densities formed above */
+    double cL = sound_speed(x, wL, iL, TL);
+    double cR = sound_speed(x, wR, iR, TR);
     double SL = fmin(uL - cL, uR - cR);
     double SR = fmax(uL + cL, uR + cR);
     if (SL >= 0.0) {
@@ -338,7 +403,14 @@ static void riemann(int solver, int d, int nvar, int de, double gamma, double gm
 void or_riemann_flux(int solver, int d, int nvar, double gamma, const double *qL, const double *qR,
                      double *flux)
 {
-    riemann(solver, d, nvar, 0, gamma, gamma - 1.0, qL, qR, flux, NULL);
+    Ctx x;
+    memset(&x, 0, sizeof x);
+    x.nvar = nvar;
+    x.gamma = gamma;
+    x.gm1 = gamma - 1.0;
+    x.inv_gm1 = 1.0 / x.gm1;
+    x.eos = OR_EOS_GAS;
+    riemann(solver, d, &x, qL, qR, flux, NULL);
 }
 
 /* ------------------------------------------------------------------ limiters */
@@ -512,6 +584,14 @@ static int ctx_init(Ctx *x, const or_config *c)
     x->gm1 = c->gamma - 1.0;
     x->inv_gm1 = 1.0 / x->gm1;
     x->de = c->dual_energy ? 1 : 0;
+    x->gamma = c->gamma;
+    x->eos = c->eos;
+    x->R = c->eos_R;
+    x->arad = c->eos_arad;
+    if (c->eos != OR_EOS_GAS && c->eos != OR_EOS_GAS_RAD)
+        return OR_EINVAL;
+    if (c->eos == OR_EOS_GAS_RAD && (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0) || c->dual_energy))
+        return OR_EINVAL;
     return OR_OK;
 }
 
@@ -643,6 +723,37 @@ static long box_size(const Box *b) { return (long)b->ext[0] * b->ext[1] * b->ext
 static double kinetic_energy(const double *q)
 {
     return 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+}
+
+double or_eos_state(const or_config *c, double rho, double e, double *P, double *cs)
+{
+    Ctx x;
+    if (ctx_init(&x, c))
+        return -1.0;
+    double q[MAXV] = {0.0}, w[MAXV];
+    q[0] = rho;
+    q[4] = e;
+    double T = 0.0;
+    const double inv = prim_inv_t(&x, q, w, &T);
+    if (x.eos != OR_EOS_GAS_RAD)
+        T = 0.0;
+    if (P)
+        *P = w[4];
+    if (cs)
+        *cs = sound_speed(&x, w, inv, T);
+    return T;
+}
+
+double or_eos_energy(const or_config *c, double rho, double P)
+{
+    Ctx x;
+    if (ctx_init(&x, c))
+        return -1.0;
+    double w[MAXV] = {0.0}, q[MAXV];
+    w[0] = rho;
+    w[4] = P;
+    cons(&x, w, q);
+    return q[4];
 }
 
 double or_de_alpha(double e, double ek, double eps)
@@ -835,14 +946,14 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                         L[v] = FS[((d * 2 + 1) * nv + v) * np + ipm];
                         R[v] = FS[((d * 2 + 0) * nv + v) * np + ip];
                     }
-                    riemann(c->riemann, d, nv, x.de, c->gamma, x.gm1, L, R, Fm[d], &ufm);
+                    riemann(c->riemann, d, &x, L, R, Fm[d], &ufm);
                     for (int v = 0; v < nv; v++) {
                         L[v] = FS[((d * 2 + 1) * nv + v) * np + ip];
                         R[v] = FS[((d * 2 + 0) * nv + v) * np + ipq];
                     }
                     /* the upper face's flux is the next cell's lower-face flux once more */
                     OR_REPEATED_WORK(1);
-                    riemann(c->riemann, d, nv, x.de, c->gamma, x.gm1, L, R, Fp[d], &ufp);
+                    riemann(c->riemann, d, &x, L, R, Fp[d], &ufp);
                     OR_REPEATED_WORK(0);
                     if (c->geom == OR_CART) {
                         double mu = dt / dxc(c, d, cidx[d]);
@@ -974,8 +1085,9 @@ int or_compute_dt(const or_config *c, const double *U, double *dt)
                     bad = 1;
                     continue;
                 }
-                double inv = prim_inv(&x, q, w);
-                double cs = sqrt(c->gamma * w[4] * inv);
+                double T = 0.0;
+                double inv = prim_inv_t(&x, q, w, &T);
+                double cs = sound_speed(&x, w, inv, T);
                 double s = 0.0;
                 for (int d = 0; d < 3; d++)
                     if (x.act[d])

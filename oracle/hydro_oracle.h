@@ -34,6 +34,7 @@ enum { OR_HLL = 0, OR_HLLC = 1 };
 enum { OR_LIM_NONE = 0, OR_LIM_MINMOD = 1, OR_LIM_VANLEER = 2, OR_LIM_VANALBADA = 3, OR_LIM_MLP = 4 };
 enum { OR_BC_PERIODIC = 0, OR_BC_TRANSMISSIVE = 1, OR_BC_REFLECTIVE = 2 };
 enum { OR_GRAV_NONE = 0, OR_GRAV_UNIFORM = 1, OR_GRAV_POINT = 2, OR_GRAV_POINT_MONOPOLE = 3 };
+enum { OR_EOS_GAS = 0, OR_EOS_GAS_RAD = 1 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENONPHYS = -3, OR_ENOMEM = -5 };
 
 #define OR_MLP_NPARAM 1249   /* 4*32+32 + 32*32+32 + 32+1 */
@@ -57,6 +58,10 @@ typedef struct {
     int dual_energy;          /* 1: the last field is the monitored internal energy e (Sect. 2.4,
                                  eq. pressure_fix); needs HLLC */
     double de_eps;            /* the criterion epsilon of the blend factor alpha (paper: 1e-6) */
+    int eos;                  /* OR_EOS_GAS (eq. eos_gas) or OR_EOS_GAS_RAD (eqs. eos_gp_rad_ein,
+                                 eos_gp_rad, cs_gp_rad; not with dual_energy) */
+    double eos_R;             /* gas + radiation: specific gas constant k_b / (mu m_u) */
+    double eos_arad;          /* gas + radiation: radiation constant a_r */
 } or_config;
 
 /* Full step of interior U (layout [nvar][n3][n2][n1]) with time step dt into Unew.
@@ -77,6 +82,13 @@ void or_totals(const or_config *c, const double *U, double *tot);
 
 /* Enclosed mass M_enc(r_i) per radial shell (spherical wedge, Sect. 2.2 eq. internal_gravity). */
 int or_enclosed_mass(const or_config *c, const double *U, double *menc);
+
+/* EoS of configuration c at rest: the temperature (0 for the ideal gas) of internal energy e per
+ * unit volume at density rho, with its pressure *P and sound speed *cs (Sect. 2.3). */
+double or_eos_state(const or_config *c, double rho, double e, double *P, double *cs);
+
+/* Internal energy per unit volume of density rho and pressure P (Sect. 2.3). */
+double or_eos_energy(const or_config *c, double rho, double P);
 
 /* Blend factor alpha of the internal-energy monitor (Sect. 2.4) for internal energy e and kinetic
  * energy e_k (per unit volume) and the criterion eps. */

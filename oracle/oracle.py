@@ -20,6 +20,7 @@ RIEMANN = {"hll": 0, "hllc": 1}
 LIMITER = {"none": 0, "minmod": 1, "vanleer": 2, "vanalbada": 3, "mlp": 4}
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 GRAVITY = {"none": 0, "uniform": 1, "point": 2, "point_monopole": 3}
+EOS = {"gas": 0, "gas_rad": 1}
 OK, EINVAL, ENONPHYS, ENOMEM = 0, -1, -3, -5
 MLP_NPARAM = 1249
 
@@ -33,6 +34,7 @@ class OrConfig(C.Structure):
         ("riemann", C.c_int), ("limiter", C.c_int), ("bc", (C.c_int * 2) * 3),
         ("gravity", C.c_int), ("g0", C.c_double * 3), ("G", C.c_double), ("Mc", C.c_double),
         ("mlp", _DP), ("dual_energy", C.c_int), ("de_eps", C.c_double),
+        ("eos", C.c_int), ("eos_R", C.c_double), ("eos_arad", C.c_double),
     ]
 
 
@@ -59,6 +61,10 @@ def lib(path: str = LIB_PATH):
         L.or_enclosed_mass.argtypes = [cp, _DP, _DP]
         L.or_riemann_flux.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _DP, _DP, _DP]
         L.or_riemann_flux.restype = None
+        L.or_eos_state.argtypes = [C.POINTER(OrConfig), C.c_double, C.c_double, _DP, _DP]
+        L.or_eos_state.restype = C.c_double
+        L.or_eos_energy.argtypes = [C.POINTER(OrConfig), C.c_double, C.c_double]
+        L.or_eos_energy.restype = C.c_double
         L.or_de_alpha.argtypes = [C.c_double, C.c_double, C.c_double]
         L.or_de_alpha.restype = C.c_double
         L.or_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
@@ -87,6 +93,10 @@ def _ptr(a: np.ndarray):
 
 def _get(p, k):
     return p[k] if isinstance(p, dict) else getattr(p, k)
+
+
+def _opt(p, k, default):
+    return p.get(k, default) if isinstance(p, dict) else getattr(p, k, default)
 
 
 class Oracle:
@@ -120,6 +130,9 @@ class Oracle:
         c.G = float(_get(prob, "G"))
         c.Mc = float(_get(prob, "Mc"))
         c.dual_energy = 1 if dual else 0
+        c.eos = EOS[_opt(prob, "eos", "gas")]
+        c.eos_R = float(_opt(prob, "eos_R", 0.0))
+        c.eos_arad = float(_opt(prob, "eos_arad", 0.0))
         c.de_eps = float(getattr(prob, "de_eps", 1e-6)) if not isinstance(prob, dict) else float(prob.get("de_eps", 1e-6))
         self._mlp = None
         if mlp_weights is not None:
@@ -211,6 +224,15 @@ class Oracle:
             steps += 1
             dts.append(dt)
         return U, t, steps, dts
+
+    def eos_state(self, rho: float, e: float):
+        """(T, P, c_s) of internal energy e per unit volume at density rho (Sect. 2.3)."""
+        P, cs = C.c_double(), C.c_double()
+        T = self._L.or_eos_state(self._cfgp(), float(rho), float(e), C.byref(P), C.byref(cs))
+        return T, P.value, cs.value
+
+    def eos_energy(self, rho: float, P: float) -> float:
+        return self._L.or_eos_energy(self._cfgp(), float(rho), float(P))
 
 
 def riemann_flux(solver: str, d: int, gamma: float, qL, qR) -> np.ndarray:

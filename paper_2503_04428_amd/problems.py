@@ -55,6 +55,9 @@ class Problem:
     meta: dict = field(default_factory=dict)
     dual_energy: bool = False     # last field = monitored internal energy e (Sect. 2.4)
     de_eps: float = 1e-6          # criterion of the blend factor alpha
+    eos: str = "gas"              # "gas" (eq. eos_gas) or "gas_rad" (gas + radiation, Sect. 2.3)
+    eos_R: float = 0.0            # gas + radiation: specific gas constant k_b / (mu m_u)
+    eos_arad: float = 0.0         # gas + radiation: radiation constant
 
     @property
     def nvar(self) -> int:
@@ -533,3 +536,43 @@ def acoustic_wave1d(n: int = 128, amp: float = 1e-3, ng: int = 2, limiter: str =
                    nscalar=0, gamma=gamma, cfl=0.5, riemann="hllc", limiter=limiter,
                    bc=[["periodic"] * 2, ["periodic"] * 2, ["periodic"] * 2], U0=U)
 
+
+
+def with_gas_rad(prob: Problem, R: float = 1.0, arad: float = 30.0) -> Problem:
+    """The same problem with the gas + radiation EoS (Sect. 2.3), re-initialised so that its
+    pressures (hence its dynamics) are those of the ideal-gas state: each cell's temperature solves
+    P = rho R T + arad T^4 / 3 and E = e(T) + |m|^2 / (2 rho).  With R = 1, arad = 30, rho = 1 and
+    T = 1, P_r / P_g = 10: radiation-dominated."""
+    U = prob.U0.copy()
+    g = prob.gamma
+    ke = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
+    p = (g - 1.0) * (U[4] - ke)
+    rho = U[0]
+    # temperature from P by bisection on the monotone residual (host-side set-up only)
+    lo = np.zeros_like(p)
+    hi = np.minimum(p / (rho * R), (3.0 * p / arad) ** 0.25) * (1 + 1e-12) + 1e-300
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        f = rho * R * mid + arad * mid ** 4 / 3.0 - p
+        hi = np.where(f > 0, mid, hi)
+        lo = np.where(f > 0, lo, mid)
+    T = 0.5 * (lo + hi)
+    U[4] = rho * R * T / (g - 1.0) + arad * T ** 4 + ke
+    return prob.with_(name=prob.name + "+rad", U0=U, eos="gas_rad", eos_R=float(R), eos_arad=float(arad))
+
+
+def rad_wall1d(n: int = 400, u0: float = -3.0, R: float = 1.0, arad: float = 30.0) -> Problem:
+    """Uniform radiation-dominated gas (rho 1, T 1, P_r / P_g = 10) streaming at u0 into a
+    reflective wall at x = 0: a strong shock whose compression tends to 7 (adiabatic index 4/3)."""
+    g = 5.0 / 3.0
+    f = np.linspace(0.0, 1.0, n + 1)
+    U = np.zeros((5, 1, 1, n))
+    rho, T = 1.0, 1.0
+    U[0] = rho
+    U[1] = rho * u0
+    U[4] = rho * R * T / (g - 1.0) + arad * T ** 4 + 0.5 * rho * u0 * u0
+    return Problem(name="rad_wall", ndim=1, geom="cart", n=(n, 1, 1), ng=2,
+                   faces=[ghost_faces(f, 2, "reflective", "transmissive"), np.array([0.0, 1.0]), np.array([0.0, 1.0])],
+                   nscalar=0, gamma=g, cfl=0.5, riemann="hllc", limiter="vanleer",
+                   bc=[["reflective", "transmissive"], ["periodic"] * 2, ["periodic"] * 2], U0=U,
+                   eos="gas_rad", eos_R=R, eos_arad=arad)
