@@ -194,9 +194,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the Sedov cube")
-    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod", "boosted"],
+    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod", "boosted", "rad"],
                     help="sedov (default, the headline line); rt, wedge, sod, boosted (Sedov in a moving "
-                         "medium with the internal-energy monitor, FP64) measure the other workloads")
+                         "medium with the internal-energy monitor, FP64), rad (Sedov with the gas + "
+                         "radiation EoS, FP64) measure the other workloads")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
@@ -231,6 +232,11 @@ def main():
         prob = problems.boosted_sedov3d(n=args.n, eps=1e-3)
         wl = (f"boosted-sedov3d-{args.n}^3 with the internal-energy monitor (periodic, 8 fields, HLLC, "
               f"van Leer, eps 1e-3)")
+        args.forms = "fp64"
+    elif args.workload == "rad":
+        prob = problems.with_gas_rad(problems.sedov3d(n=args.n))
+        wl = (f"sedov3d-{args.n}^3 with the gas + radiation EoS (R 1, a 30; 7 fields, HLLC, van Leer, "
+              f"CFL 0.5)")
         args.forms = "fp64"
     elif args.workload == "rt":
         prob = problems.rt3d()

@@ -55,6 +55,7 @@ enum { HX_LIMITER_NONE = 0, HX_LIMITER_MINMOD = 1, HX_LIMITER_VANLEER = 2, HX_LI
 enum { HX_PRECISION_FP64 = 0, HX_PRECISION_FP32 = 1 };
 enum { HX_BOUNDARY_PERIODIC = 0, HX_BOUNDARY_TRANSMISSIVE = 1, HX_BOUNDARY_REFLECTIVE = 2 };
 enum { HX_GRAVITY_NONE = 0, HX_GRAVITY_UNIFORM = 1, HX_GRAVITY_POINT = 2, HX_GRAVITY_POINT_MONOPOLE = 3 };
+enum { HX_EOS_GAS = 0, HX_EOS_GAS_RAD = 1 };
 
 #define HX_MLP_NPARAM 1249 /* 4->32->32->1: W1[32][4] b1[32] W2[32][32] b2[32] w3[32] b3 */
 
@@ -83,6 +84,14 @@ typedef struct {
                                the total- and internal-energy updates); needs FP64, HLLC, a
                                limiter other than the learned one and nscalar <= 3.  0: off */
     double de_eps;          /* the blend criterion epsilon (the paper uses 1e-6), >= 0 */
+    int eos;                /* HX_EOS_GAS: ideal gas (eq. eos_gas).  HX_EOS_GAS_RAD: ideal gas plus
+                               radiation (Sect. 2.3, eqs. eos_gp_rad_ein and eos_gp_rad:
+                               e = rho R T/(gamma-1) + a T^4, P = rho R T + a T^4/3; T from e or P by
+                               ten Newton steps from the smaller of the gas-only and radiation-only
+                               temperatures; sound speed of eq. cs_gp_rad); needs FP64, no
+                               internal-energy monitor and a limiter other than the learned one */
+    double eos_R;           /* HX_EOS_GAS_RAD: specific gas constant k_b/(mu m_u), > 0 */
+    double eos_arad;        /* HX_EOS_GAS_RAD: radiation constant a, >= 0 */
 } hx_config;
 
 /* Device bytes the caller must provide to hx_create for this configuration, or 0 if the

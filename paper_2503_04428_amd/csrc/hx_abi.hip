@@ -122,6 +122,18 @@ hx_status validate(const hx_config* c)
         if (!(c->de_eps >= 0.0))
             return fail(HX_EINVAL, "de_eps must be >= 0");
     }
+    if (c->eos != HX_EOS_GAS && c->eos != HX_EOS_GAS_RAD)
+        return fail(HX_EINVAL, "unknown EoS %d", c->eos);
+    if (c->eos == HX_EOS_GAS_RAD) {
+        if (c->precision != HX_PRECISION_FP64)
+            return fail(HX_EINVAL, "the gas + radiation EoS is built for the FP64 form");
+        if (c->dual_energy)
+            return fail(HX_EINVAL, "the gas + radiation EoS is not built with the internal-energy monitor");
+        if (c->limiter == HX_LIMITER_MLP)
+            return fail(HX_EINVAL, "the gas + radiation EoS is not built with the learned limiter");
+        if (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0) || !std::isfinite(c->eos_R) || !std::isfinite(c->eos_arad))
+            return fail(HX_EINVAL, "the gas + radiation EoS needs eos_R > 0 and eos_arad >= 0");
+    }
     if (c->precision != HX_PRECISION_FP64 && c->precision != HX_PRECISION_FP32)
         return fail(HX_EINVAL, "unknown precision %d", c->precision);
     if (!(c->gamma > 1.0) || !(c->cfl > 0.0))
@@ -367,6 +379,9 @@ hx::DtParams dt_params(hx_ctx* x)
     p.plane = x->ncells;
     p.gamma = x->cfg.gamma;
     p.gm1 = x->cfg.gamma - 1.0;
+    p.eos = x->cfg.eos;
+    p.eos_R = x->cfg.eos_R;
+    p.eos_arad = x->cfg.eos_arad;
     p.geo = x->geo;
     p.partial = at<double>(x, x->L.partial);
     p.flag = at<int>(x, x->L.flag);
@@ -417,6 +432,8 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     p.dtpart = at<double>(x, x->L.dtpart);
     p.mlp = at<float>(x, x->L.mlp);
     p.de_eps = c.de_eps;
+    p.eos_R = c.eos_R;
+    p.eos_arad = c.eos_arad;
     const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC;
     if (c.limiter == HX_LIMITER_MLP && !x->have_mlp)
         return fail(HX_ESTATE, "the learned limiter needs hx_set_mlp before stepping");
@@ -424,6 +441,8 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     auto sweep = [&](int* occ) -> hipError_t {
         if (c.dual_energy)
             return hx::launch_sweep_fp64_de(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+        if (c.eos == HX_EOS_GAS_RAD)
+            return hx::launch_sweep_fp64_rad(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (c.limiter == HX_LIMITER_MLP)
             return hx::launch_sweep_fp32_mlp(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (x->fp32)

@@ -34,19 +34,104 @@ struct Num<float> {
 template <typename R>
 struct Gas {
     R gm1, inv_gm1, gamma;
+    R Rg, arad;  // gas + radiation EoS: specific gas constant k_b/(mu m_u), radiation constant
 };
+
+// ---------------------------------------------------------------- gas + radiation EoS
+// Sect. 2.3, eqs. eos_gp_rad_ein and eos_gp_rad: e = rho Rg T/(gamma-1) + arad T^4 and
+// P = rho Rg T + arad T^4 / 3 (FP64).  The temperature follows from e (or from P) by a fixed
+// count of Newton steps started from the smaller of the gas-only and radiation-only temperatures,
+// an upper bound from which the iteration decreases monotonically to the root.
+constexpr int EOS_NEWTON_STEPS = 10;
+
+__device__ __forceinline__ double t4(double T) { return (T * T) * (T * T); }
+
+// K independent temperatures in one loop (from e, or from P with FROM_P), so that the dependent
+// chains of their Newton steps overlap; each chain computes exactly what a single solve does
+template <bool FROM_P, int K>
+__device__ __forceinline__ void temp_solve(const Gas<double>& g, const double* rho, const double* x, double* T)
+{
+    double c[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+        c[j] = FROM_P ? rho[j] * g.Rg : (rho[j] * g.Rg) / g.gm1;
+        const double tg = x[j] / c[j];
+        const double tr = FROM_P ? sqrt(sqrt((3.0 * x[j]) / g.arad)) : sqrt(sqrt(x[j] / g.arad));
+        T[j] = tg < tr ? tg : tr;
+    }
+#pragma unroll 1
+    for (int it = 0; it < EOS_NEWTON_STEPS; it++) {
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const double Tj = T[j];
+            double f, fp;
+            if (FROM_P) {
+                f = c[j] * Tj + (g.arad * t4(Tj)) / 3.0 - x[j];
+                fp = c[j] + (4.0 * g.arad * ((Tj * Tj) * Tj)) / 3.0;
+            } else {
+                f = c[j] * Tj + g.arad * t4(Tj) - x[j];
+                fp = c[j] + 4.0 * g.arad * ((Tj * Tj) * Tj);
+            }
+            T[j] = Tj - f / fp;
+        }
+    }
+}
+
+__device__ __forceinline__ double temp_from_e(const Gas<double>& g, double rho, double e)
+{
+    double T;
+    temp_solve<false, 1>(g, &rho, &e, &T);
+    return T;
+}
+
+__device__ __forceinline__ double temp_from_p(const Gas<double>& g, double rho, double P)
+{
+    double T;
+    temp_solve<true, 1>(g, &rho, &P, &T);
+    return T;
+}
+
+// internal energy per unit volume at temperature T
+__device__ __forceinline__ double rad_energy(const Gas<double>& g, double rho, double T)
+{
+    return ((rho * g.Rg) * T) / g.gm1 + g.arad * t4(T);
+}
+
+// pressure at temperature T
+__device__ __forceinline__ double rad_pressure(const Gas<double>& g, double rho, double T)
+{
+    return (rho * g.Rg) * T + (g.arad * t4(T)) / 3.0;
+}
+
+// sound speed from primitives w, reciprocal density inv and (gas + radiation) temperature T:
+// eq. eos_gas, or eq. cs_gp_rad with alpha = P_r / P_g
+template <typename R, int EOS>
+__device__ __forceinline__ R sound_speed(const Gas<R>& g, const R* w, R inv, R T)
+{
+    if constexpr (EOS == 0) {
+        return Num<R>::sqrt_(g.gamma * w[4] * inv);
+    } else {
+        static_assert(sizeof(R) == 8, "the gas + radiation EoS is built for FP64");
+        const double pg = (w[0] * g.Rg) * T;
+        const double pr = (g.arad * t4(T)) / 3.0;
+        const double al = pr / pg;
+        const double num = g.gamma / g.gm1 + 20.0 * al + 16.0 * (al * al);
+        const double den = 1.0 / g.gm1 + 12.0 * al;
+        return sqrt((num / den) * (pg * inv));
+    }
+}
 
 // ---------------------------------------------------------------- EoS
 
 // primitives from conserved.  DE: the last field is the monitored internal energy e, which is
 // its own primitive (per unit volume, like the pressure); the passive scalars before it are
 // carried per unit mass.
-template <typename R, int NV, bool DE>
+template <typename R, int NV, bool DE, int EOS>
 struct PrimImpl;
 
-template <int NV, bool DE>
-struct PrimImpl<double, NV, DE> {
-    static __device__ __forceinline__ double run(const Gas<double>& g, const double* q, double* w)
+template <int NV, bool DE, int EOS>
+struct PrimImpl<double, NV, DE, EOS> {
+    static __device__ __forceinline__ double run(const Gas<double>& g, const double* q, double* w, double* T)
     {
         double rho = q[0];
         double inv = 1.0 / rho;
@@ -56,7 +141,14 @@ struct PrimImpl<double, NV, DE> {
         w[1] = u1;
         w[2] = u2;
         w[3] = u3;
-        w[4] = g.gm1 * (q[4] - ke);
+        if constexpr (EOS == 1) {
+            const double Tt = temp_from_e(g, rho, q[4] - ke);
+            w[4] = rad_pressure(g, rho, Tt);
+            if (T)
+                *T = Tt;
+        } else {
+            w[4] = g.gm1 * (q[4] - ke);
+        }
 #pragma unroll
         for (int v = 5; v < NV - DE; v++)
             w[v] = q[v] * inv;
@@ -66,11 +158,12 @@ struct PrimImpl<double, NV, DE> {
     }
 };
 
-template <int NV, bool DE>
-struct PrimImpl<float, NV, DE> {
+template <int NV, bool DE, int EOS>
+struct PrimImpl<float, NV, DE, EOS> {
+    static_assert(EOS == 0, "the gas + radiation EoS is built for FP64");
     // FP32 bulk, FP64 island for the internal energy: 1/rho from the hardware reciprocal refined
     // by one FP64 Newton step, then e = E - |m|^2/(2 rho) in FP64.
-    static __device__ __forceinline__ float run(const Gas<float>& g, const float* q, float* w)
+    static __device__ __forceinline__ float run(const Gas<float>& g, const float* q, float* w, float*)
     {
         float rho = q[0];
         float r = __builtin_amdgcn_rcpf(rho);
@@ -93,11 +186,46 @@ struct PrimImpl<float, NV, DE> {
     }
 };
 
-// returns the reciprocal density used for the velocities
-template <typename R, int NV, bool DE = false>
-__device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w)
+// returns the reciprocal density used for the velocities; T (if not null) receives the
+// temperature of the gas + radiation EoS
+template <typename R, int NV, bool DE = false, int EOS = 0>
+__device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w, R* T = nullptr)
 {
-    return PrimImpl<R, NV, DE>::run(g, q, w);
+    return PrimImpl<R, NV, DE, EOS>::run(g, q, w, T);
+}
+
+// gas + radiation EoS: primitives of two conserved states (the faces of one Riemann problem) with
+// their two temperature solves in one loop; the same values as two calls of to_prim
+template <int NV>
+__device__ __forceinline__ void to_prim_rad2(const Gas<double>& g, const double* qa, const double* qb, double* wa,
+                                             double* wb, double& ia, double& ib, double& Ta, double& Tb)
+{
+    const double* q[2] = {qa, qb};
+    double* w[2] = {wa, wb};
+    double rho[2], e[2], inv[2], T[2];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        rho[j] = q[j][0];
+        inv[j] = 1.0 / rho[j];
+        const double u1 = q[j][1] * inv[j], u2 = q[j][2] * inv[j], u3 = q[j][3] * inv[j];
+        const double ke = 0.5 * (q[j][1] * u1 + q[j][2] * u2 + q[j][3] * u3);
+        w[j][0] = rho[j];
+        w[j][1] = u1;
+        w[j][2] = u2;
+        w[j][3] = u3;
+        e[j] = q[j][4] - ke;
+#pragma unroll
+        for (int v = 5; v < NV; v++)
+            w[j][v] = q[j][v] * inv[j];
+    }
+    temp_solve<false, 2>(g, rho, e, T);
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+        w[j][4] = rad_pressure(g, rho[j], T[j]);
+    ia = inv[0];
+    ib = inv[1];
+    Ta = T[0];
+    Tb = T[1];
 }
 
 // kinetic energy |m|^2 / (2 rho) of a conserved state
@@ -130,7 +258,7 @@ __device__ __forceinline__ bool positive_state(const R* q)
     return q[0] > R(0) && R(2) * q[0] * q[4] - m2 > R(0);
 }
 
-template <typename R, int NV, bool DE = false>
+template <typename R, int NV, bool DE = false, int EOS = 0>
 __device__ __forceinline__ void to_cons(const Gas<R>& g, const R* w, R* q)
 {
     R rho = w[0];
@@ -138,12 +266,44 @@ __device__ __forceinline__ void to_cons(const Gas<R>& g, const R* w, R* q)
     q[1] = rho * w[1];
     q[2] = rho * w[2];
     q[3] = rho * w[3];
-    q[4] = w[4] * g.inv_gm1 + R(0.5) * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+    if constexpr (EOS == 1) {
+        const double e = rad_energy(g, rho, temp_from_p(g, rho, w[4]));
+        q[4] = e + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+    } else {
+        q[4] = w[4] * g.inv_gm1 + R(0.5) * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+    }
 #pragma unroll
     for (int v = 5; v < NV - DE; v++)
         q[v] = rho * w[v];
     if (DE)
         q[NV - 1] = w[NV - 1];
+}
+
+// gas + radiation EoS: conserved state of primitives w whose internal energy e(rho, P) is already
+// known (rad_energy2); the same values as to_cons
+template <int NV>
+__device__ __forceinline__ void to_cons_e(const double* w, double e, double* q)
+{
+    const double rho = w[0];
+    q[0] = rho;
+    q[1] = rho * w[1];
+    q[2] = rho * w[2];
+    q[3] = rho * w[3];
+    q[4] = e + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+#pragma unroll
+    for (int v = 5; v < NV; v++)
+        q[v] = rho * w[v];
+}
+
+// gas + radiation EoS: internal energies of two primitive states (solves in one loop)
+__device__ __forceinline__ void rad_energy2(const Gas<double>& g, const double* wa, const double* wb, double& ea,
+                                            double& eb)
+{
+    const double rho[2] = {wa[0], wb[0]}, P[2] = {wa[4], wb[4]};
+    double T[2];
+    temp_solve<true, 2>(g, rho, P, T);
+    ea = rad_energy(g, rho[0], T[0]);
+    eb = rad_energy(g, rho[1], T[1]);
 }
 
 // physical flux along axis D from primitives w and conserved q of the same state
@@ -168,19 +328,24 @@ __device__ __forceinline__ void phys_flux(const R* w, const R* q, R* f)
 // HLL / HLLC with Davis wave speeds (Sect. 3.2; textbook solvers the paper cites)
 // uf (if not null) receives the interface velocity: the contact speed S* in the HLLC star
 // region, else the normal velocity of the upwind side (HLL leaves it unset).
-template <typename R, int NV, int D, bool DE = false>
+template <typename R, int NV, int D, bool DE = false, int EOS = 0>
 __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL, const R* qR, R* F,
                                         R* uf = nullptr)
 {
     using N = Num<R>;
     R wL[NV], wR[NV];
-    const R iL = to_prim<R, NV, DE>(g, qL, wL);
-    const R iR = to_prim<R, NV, DE>(g, qR, wR);
+    R TL = R(0), TR = R(0), iL, iR;
+    if constexpr (EOS == 1) {
+        to_prim_rad2<NV>(g, qL, qR, wL, wR, iL, iR, TL, TR);
+    } else {
+        iL = to_prim<R, NV, DE, EOS>(g, qL, wL, &TL);
+        iR = to_prim<R, NV, DE, EOS>(g, qR, wR, &TR);
+    }
     R rL = wL[0], rR = wR[0];
     R uL = wL[1 + D], uR = wR[1 + D];
     R pL = wL[4], pR = wR[4];
-    R cL = N::sqrt_(g.gamma * pL * iL);
-    R cR = N::sqrt_(g.gamma * pR * iR);
+    R cL = sound_speed<R, EOS>(g, wL, iL, TL);
+    R cR = sound_speed<R, EOS>(g, wR, iR, TR);
     R SL = fmin(uL - cL, uR - cR);
     R SR = fmax(uL + cL, uR + cR);
     if (solver == HX_HLL) {

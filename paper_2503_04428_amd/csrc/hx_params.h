@@ -64,6 +64,8 @@ struct SweepParams {
     int kz;              // z planes per block (3D)
     const float* mlp;    // learned limiter weights (FP32 master copy)
     double de_eps;       // criterion of the internal-energy monitor's blend factor
+    double eos_R;        // gas + radiation EoS: specific gas constant and radiation constant
+    double eos_arad;
 };
 
 }  // namespace hx

@@ -2,6 +2,7 @@
 // FP32 <-> FP64 state conversions of the FP32 form.
 #include <hip/hip_runtime.h>
 
+#include "hx_device.h"
 #include "hx_launch.h"
 
 namespace hx {
@@ -25,7 +26,8 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // CFL signal rate of every interior cell, sum_d (|u_d| + c_s) / dx_d, maximised per block.
-// FP64 throughout (the FP32 form converts its state on load), in the oracle's operation order.
+// FP64 throughout (the FP32 form converts its state on load), in the oracle's operation order;
+// P and c_s from the ideal-gas or the gas + radiation EoS (Sect. 2.3).
 template <typename R>
 __global__ void __launch_bounds__(RB) dt_partial_kernel(const DtParams p)
 {
@@ -50,12 +52,30 @@ __global__ void __launch_bounds__(RB) dt_partial_kernel(const DtParams p)
         double inv = 1.0 / rho;
         double u1 = q[1] * inv, u2 = q[2] * inv, u3 = q[3] * inv;
         double ke = 0.5 * (q[1] * u1 + q[2] * u2 + q[3] * u3);
-        double pr = p.gm1 * (q[4] - ke);
-        if (!fin || !(rho > 0.0) || !(pr > 0.0)) {
-            bad = 1;
-            continue;
+        double pr, cs;
+        if (p.eos == 1) {
+            Gas<double> g;
+            g.gamma = p.gamma;
+            g.gm1 = p.gm1;
+            g.inv_gm1 = 1.0 / p.gm1;
+            g.Rg = p.eos_R;
+            g.arad = p.eos_arad;
+            const double T = temp_from_e(g, rho, q[4] - ke);
+            pr = (rho * g.Rg) * T + (g.arad * t4(T)) / 3.0;
+            if (!fin || !(rho > 0.0) || !(pr > 0.0)) {
+                bad = 1;
+                continue;
+            }
+            const double w[5] = {rho, u1, u2, u3, pr};
+            cs = sound_speed<double, 1>(g, w, inv, T);
+        } else {
+            pr = p.gm1 * (q[4] - ke);
+            if (!fin || !(rho > 0.0) || !(pr > 0.0)) {
+                bad = 1;
+                continue;
+            }
+            cs = sqrt(p.gamma * pr * inv);
         }
-        double cs = sqrt(p.gamma * pr * inv);
         double u[3] = {u1, u2, u3};
         double s = 0.0;
         for (int d = 0; d < p.ndim; d++) {

@@ -40,8 +40,9 @@ struct MinWaves {
 #ifdef HX_MINW_FP64
     static constexpr int fp64 = HX_MINW_FP64;
 #else
-    // (the internal-energy monitor's extra state spills at two waves even with 6 fields)
-    static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV && SPEC != 3 ? 2 : 1;
+    // (the internal-energy monitor's extra state and the gas + radiation EoS's Newton solves spill
+    // at two waves even with 5 or 6 fields)
+    static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV && SPEC < 3 ? 2 : 1;
 #endif
     static constexpr int value = sizeof(R) == 8 ? fp64 : HX_MINW_FP32;
 };
@@ -108,9 +109,10 @@ __device__ __forceinline__ R from_right(R v)
 }
 
 // CFL signal rate sum_d (|u_d| + c_s)/dx_d of a conserved state, in FP64, in the operation order
-// of the reference definition; returns a negative value for a non-physical state
-template <typename R, int NV, int NDIM>
-__device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const double* wd)
+// of the reference definition (EOS = 1: P and c_s of the gas + radiation EoS); returns a negative
+// value for a non-physical state
+template <typename R, int NV, int NDIM, int EOS = 0>
+__device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const double* wd, const Gas<R>& eg)
 {
     double q[NV];
     bool fin = true;
@@ -123,10 +125,20 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
     const double inv = 1.0 / rho;
     const double u1 = q[1] * inv, u2 = q[2] * inv, u3 = q[3] * inv;
     const double ke = 0.5 * (q[1] * u1 + q[2] * u2 + q[3] * u3);
-    const double pr = (gamma - 1.0) * (q[4] - ke);
-    if (!fin || !(rho > 0.0) || !(pr > 0.0))
-        return -1.0;
-    const double cs = sqrt(gamma * pr * inv);
+    double pr, cs;
+    if constexpr (EOS == 1) {
+        const double T = temp_from_e(eg, rho, q[4] - ke);
+        pr = (rho * eg.Rg) * T + (eg.arad * t4(T)) / 3.0;
+        if (!fin || !(rho > 0.0) || !(pr > 0.0))
+            return -1.0;
+        const double w[5] = {rho, u1, u2, u3, pr};
+        cs = sound_speed<double, 1>(eg, w, inv, T);
+    } else {
+        pr = (gamma - 1.0) * (q[4] - ke);
+        if (!fin || !(rho > 0.0) || !(pr > 0.0))
+            return -1.0;
+        cs = sqrt(gamma * pr * inv);
+    }
     const double u[3] = {u1, u2, u3};
     double s = 0.0;
 #pragma unroll
@@ -139,7 +151,8 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // limiter with HLLC (slope stencil of half-width 2, BF16 matrix-core network); SPEC = 0 reads the
 // limiter and the Riemann solver from the parameters; SPEC = 3 adds the internal-energy monitor
 // (Sect. 2.4: the last field is e, with eq. pressure_fix and the alpha blend; HLLC, limiter from
-// the parameters).
+// the parameters); SPEC = 4 the gas + radiation EoS (Sect. 2.3, FP64; limiter and Riemann solver
+// from the parameters).
 template <typename R, int NV, int NDIM, int GEOM, int SPEC>
 __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, SPEC>::value))
     sweep_kernel(const SweepParams p)
@@ -150,6 +163,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     constexpr int NT = BX * BY;
     constexpr bool MLP = SPEC == 2;
     constexpr bool DE = SPEC == 3;  // internal-energy monitor: the last field is e (FP64, HLLC)
+    constexpr int EOS = SPEC == 4 ? 1 : 0;  // gas + radiation EoS (FP64)
     constexpr int S = MLP ? 2 : 1;  // half-width of the slope stencil
     constexpr int RX = BX + 2 * S;
     constexpr int RY = NDIM >= 2 ? BY + 2 * S : 1;
@@ -169,7 +183,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     __shared__ __align__(16) unsigned char sMlpRaw[MLP ? sizeof(MlpShared) : 16];  // network operands
     MlpShared& sMlp = *reinterpret_cast<MlpShared*>(sMlpRaw);
     const int lim = SPEC == 1 ? HX_LIM_VANLEER : (SPEC == 2 ? HX_LIM_MLP : p.limiter);
-    const int solver = SPEC ? HX_HLLC : p.riemann;
+    const int solver = SPEC == 0 || SPEC == 4 ? p.riemann : HX_HLLC;
     double smax = 0.0;     // CFL rate of the cells this thread stores
 
     const R* __restrict__ U = (const R*)p.U;
@@ -208,6 +222,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     gas.gamma = N::from_d(p.gamma);
     gas.gm1 = N::from_d(p.gamma - 1.0);
     gas.inv_gm1 = N::from_d(1.0 / (p.gamma - 1.0));
+    gas.Rg = N::from_d(p.eos_R);
+    gas.arad = N::from_d(p.eos_arad);
 
     // images of this thread's x / y indices
     bool fx, fy;
@@ -323,7 +339,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             q[2] = -q[2];
         if (fk)
             q[3] = -q[3];
-        to_prim<R, NV, DE>(gas, q, w);
+        to_prim<R, NV, DE, EOS>(gas, q, w);
         const bool kin = NDIM < 3 || (k >= 0 && k < n2);
         if (kin && interior && bad_state<R, NV>(q, w))
             p.flag[0] = 1;
@@ -339,7 +355,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             if (fk)
                 q[3] = -q[3];
             R w[NV];
-            to_prim<R, NV, DE>(gas, q, w);
+            to_prim<R, NV, DE, EOS>(gas, q, w);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 sW[s][v][ring_lds] = w[v];
@@ -590,6 +606,19 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             du[v] = R(0);
             dlt[0][v] = dlt[1][v] = dlt[2][v] = R(0);
         }
+        // gas + radiation EoS: internal energies of the six reconstructed face states, solved
+        // once here and reused by the positivity check and the final face states
+        R ef[EOS ? 3 : 1][2];
+        auto pred_cons = [&](int d, const R* wm, const R* wp, R* um, R* up) {
+            if constexpr (EOS == 1) {
+                rad_energy2(gas, wm, wp, ef[d][0], ef[d][1]);
+                to_cons_e<NV>(wm, ef[d][0], um);
+                to_cons_e<NV>(wp, ef[d][1], up);
+            } else {
+                to_cons<R, NV, DE, EOS>(gas, wm, um);
+                to_cons<R, NV, DE, EOS>(gas, wp, up);
+            }
+        };
         {
             // x
             if constexpr (MLP) {
@@ -604,8 +633,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 wm[v] = wcur[v] - dlt[0][v];
                 wp[v] = wcur[v] + dlt[0][v];
             }
-            to_cons<R, NV, DE>(gas, wm, um);
-            to_cons<R, NV, DE>(gas, wp, up);
+            pred_cons(0, wm, wp, um, up);
             phys_flux<R, NV, 0, DE>(wm, um, fm);
             phys_flux<R, NV, 0, DE>(wp, up, fp);
 #pragma unroll
@@ -624,8 +652,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 wm[v] = wcur[v] - dlt[1][v];
                 wp[v] = wcur[v] + dlt[1][v];
             }
-            to_cons<R, NV, DE>(gas, wm, um);
-            to_cons<R, NV, DE>(gas, wp, up);
+            pred_cons(1, wm, wp, um, up);
             phys_flux<R, NV, 1, DE>(wm, um, fm);
             phys_flux<R, NV, 1, DE>(wp, up, fp);
 #pragma unroll
@@ -649,8 +676,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 wm[v] = wcur[v] - dlt[2][v];
                 wp[v] = wcur[v] + dlt[2][v];
             }
-            to_cons<R, NV, DE>(gas, wm, um);
-            to_cons<R, NV, DE>(gas, wp, up);
+            pred_cons(2, wm, wp, um, up);
             phys_flux<R, NV, 2, DE>(wm, um, fm);
             phys_flux<R, NV, 2, DE>(wp, up, fp);
 #pragma unroll
@@ -696,7 +722,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
-                to_cons<R, NV, DE>(gas, ws, qs);
+                if constexpr (EOS == 1)
+                    to_cons_e<NV>(ws, ef[d][side], qs);
+                else
+                    to_cons<R, NV, DE, EOS>(gas, ws, qs);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     qs[v] += du[v];
@@ -733,8 +762,21 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     dd[v] = dlt[d][v];
             }
         };
+        // gas + radiation EoS, fallback: the internal energy of W itself (rho and P of W -/+ 0)
+        R e0 = R(0);
+        if constexpr (EOS == 1) {
+            if (bad)
+                e0 = rad_energy(gas, wcur[0], temp_from_p(gas, wcur[0], wcur[4]));
+        }
+        // conserved state of face-state primitives ws of axis d, side
+        auto face_cons = [&](int d, int side, bool fb, const R* ws, R* out) {
+            if constexpr (EOS == 1)
+                to_cons_e<NV>(ws, fb ? e0 : ef[d][side], out);
+            else
+                to_cons<R, NV, DE, EOS>(gas, ws, out);
+        };
         // final half-step face states: cons(W -/+ delta) + du, or cons(W -/+ 0) in the fallback
-        auto face_state = [&](const R* dd, int side, R* out) {
+        auto face_state = [&](int d, const R* dd, int side, R* out) {
             R ws[NV];
             if (REFORM) {
                 // du and the held slopes are zero in the fallback; recomputed slopes are zeroed here
@@ -743,7 +785,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     const R dv = RESLOPE && bad ? R(0) : dd[v];
                     ws[v] = side ? wcur[v] + dv : wcur[v] - dv;
                 }
-                to_cons<R, NV, DE>(gas, ws, out);
+                face_cons(d, side, bad, ws, out);
                 if (!bad) {
 #pragma unroll
                     for (int v = 0; v < NV; v++)
@@ -754,7 +796,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
-            to_cons<R, NV, DE>(gas, ws, out);
+            face_cons(d, side, false, ws, out);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 out[v] += du[v];
@@ -762,7 +804,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ws[v] = side ? wcur[v] + R(0) : wcur[v] - R(0);
-                to_cons<R, NV, DE>(gas, ws, out);
+                face_cons(d, side, true, ws, out);
             }
         };
         // sources of the cell half-step state uh = U^n + du (U^n in the fallback): gravity
@@ -805,9 +847,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             {
                 R dd[NV], qmz[NV];
                 axis_dl(2, dd);
-                face_state(dd, 0, qmz);
-                riemann<R, NV, 2, DE>(solver, gas, uzp, qmz, Fz, DE ? &ufz : nullptr);
-                face_state(dd, 1, uzp);
+                face_state(2, dd, 0, qmz);
+                riemann<R, NV, 2, DE, EOS>(solver, gas, uzp, qmz, Fz, DE ? &ufz : nullptr);
+                face_state(2, dd, 1, uzp);
             }
             // finish plane k-1 with its z terms and sources, then store it
             if (interior && k - 1 >= k0) {
@@ -849,7 +891,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 for (int v = 0; v < NV; v++)
                     Un[(long long)v * p.plane + off] = acc[v];
                 double wd[3] = {wx, wy, GEOM == HX_CART ? w2prev : p.geo.rabs[gx] * p.geo.sabs[gy] * w2prev};
-                const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
+                const double sr = cfl_rate<R, NV, NDIM, EOS>(acc, p.gamma, wd, gas);
                 if (sr < 0.0)
                     p.flag[0] = 1;
                 smax = fmax(smax, sr);
@@ -867,18 +909,18 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             {
                 R dd[NV], qpx[NV];
                 axis_dl(0, dd);
-                face_state(dd, 1, qpx);
+                face_state(0, dd, 1, qpx);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     L[v] = from_left<BX>(qpx[v]);
-                face_state(dd, 0, qmx);
+                face_state(0, dd, 0, qmx);
             }
             if (tx == 0) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     L[v] = qmx[v];
             }
-            riemann<R, NV, 0, DE>(solver, gas, L, qmx, Fx, DE ? &ufx : nullptr);
+            riemann<R, NV, 0, DE, EOS>(solver, gas, L, qmx, Fx, DE ? &ufx : nullptr);
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 Fxr[v] = from_right<BX>(Fx[v]);
@@ -929,8 +971,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             if (NDIM >= 2) {
                 R dd[NV], qpy[NV];
                 axis_dl(1, dd);
-                face_state(dd, 0, qmy);
-                face_state(dd, 1, qpy);
+                face_state(1, dd, 0, qmy);
+                face_state(1, dd, 1, qpy);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     sFy[v][tid] = qpy[v];
@@ -941,7 +983,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     L[v] = ty > 0 ? sFy[v][tid - BX] : qmy[v];
-                riemann<R, NV, 1, DE>(solver, gas, L, qmy, Fy, DE ? &ufy : nullptr);
+                riemann<R, NV, 1, DE, EOS>(solver, gas, L, qmy, Fy, DE ? &ufy : nullptr);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     sGy[v][tid] = Fy[v];
@@ -988,7 +1030,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 double pu = 0.0;
                 if (NDIM < 3) {
                     R wu[NV];
-                    to_prim<R, NV, DE>(gas, uh, wu);
+                    to_prim<R, NV, DE, EOS>(gas, uh, wu);
                     pu = (double)wu[4];
                 }
                 double Xt, Tt = 0.0, gtg = 0.0;
@@ -1032,7 +1074,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 for (int v = 0; v < NV; v++)
                     Un[(long long)v * p.plane + off] = acc[v];
                 double wd[3] = {wx, wy, 0.0};
-                const double sr = cfl_rate<R, NV, NDIM>(acc, p.gamma, wd);
+                const double sr = cfl_rate<R, NV, NDIM, EOS>(acc, p.gamma, wd, gas);
                 if (sr < 0.0)
                     p.flag[0] = 1;
                 smax = fmax(smax, sr);

@@ -24,6 +24,7 @@ LIMITER = {"none": 0, "minmod": 1, "vanleer": 2, "vanalbada": 3, "mlp": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 GRAVITY = {"none": 0, "uniform": 1, "point": 2, "point_monopole": 3}
+EOS = {"gas": 0, "gas_rad": 1}
 
 _DP = C.POINTER(C.c_double)
 
@@ -35,6 +36,7 @@ class HxConfig(C.Structure):
         ("riemann", C.c_int), ("limiter", C.c_int), ("precision", C.c_int),
         ("bc", (C.c_int * 2) * 3), ("gravity", C.c_int), ("g0", C.c_double * 3),
         ("G", C.c_double), ("Mc", C.c_double), ("dual_energy", C.c_int), ("de_eps", C.c_double),
+        ("eos", C.c_int), ("eos_R", C.c_double), ("eos_arad", C.c_double),
     ]
 
 
@@ -133,6 +135,9 @@ def make_config(prob, precision: str | None = None):
     c.Mc = float(_get(prob, "Mc"))
     c.dual_energy = 1 if _opt(prob, "dual_energy", False) else 0
     c.de_eps = float(_opt(prob, "de_eps", 1e-6))
+    c.eos = EOS[_opt(prob, "eos", "gas")]
+    c.eos_R = float(_opt(prob, "eos_R", 0.0))
+    c.eos_arad = float(_opt(prob, "eos_arad", 0.0))
     return c, faces
 
 

@@ -548,15 +548,30 @@ def with_gas_rad(prob: Problem, R: float = 1.0, arad: float = 30.0) -> Problem:
     ke = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
     p = (g - 1.0) * (U[4] - ke)
     rho = U[0]
-    # temperature from P by bisection on the monotone residual (host-side set-up only)
-    lo = np.zeros_like(p)
-    hi = np.minimum(p / (rho * R), (3.0 * p / arad) ** 0.25) * (1 + 1e-12) + 1e-300
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        f = rho * R * mid + arad * mid ** 4 / 3.0 - p
-        hi = np.where(f > 0, mid, hi)
-        lo = np.where(f > 0, lo, mid)
-    T = 0.5 * (lo + hi)
+    # temperature from P by bisection on the monotone residual (host-side set-up only): the gas-only
+    # and radiation-only temperatures bound the root from above, and half the smaller one (each
+    # term of P is below P) from below, so 60 halvings reach full precision
+    T = np.empty_like(p)
+    pf, cgf, Tf = p.reshape(-1), (rho * R).reshape(-1), T.reshape(-1)
+    for a in range(0, pf.size, 1 << 16):  # cache-sized chunks
+        pc, cg = pf[a:a + (1 << 16)], cgf[a:a + (1 << 16)]
+        with np.errstate(divide="ignore"):
+            hi = np.minimum(pc / cg, (3.0 * pc / arad) ** 0.25) * (1 + 1e-12)
+        lo = 0.5 * hi
+        mid = np.empty_like(pc)
+        f = np.empty_like(pc)
+        for _ in range(60):
+            np.add(lo, hi, out=mid)
+            mid *= 0.5
+            np.multiply(mid, mid, out=f)
+            f *= f
+            f *= arad / 3.0
+            f += cg * mid
+            f -= pc
+            up = f > 0
+            np.copyto(hi, mid, where=up)
+            np.copyto(lo, mid, where=~up)
+        Tf[a:a + (1 << 16)] = 0.5 * (lo + hi)
     U[4] = rho * R * T / (g - 1.0) + arad * T ** 4 + ke
     return prob.with_(name=prob.name + "+rad", U0=U, eos="gas_rad", eos_R=float(R), eos_arad=float(arad))
 

@@ -42,7 +42,8 @@ def test_workspace_bytes_for_the_workloads():
     assert H.workspace_bytes(P.sedov3d(n=64), precision="fp32") < sizes["sedov"]
 
 
-@pytest.mark.parametrize("bad", ["ndim", "nghost", "faces", "periodic", "gravity", "r0", "nscalar", "mlp"])
+@pytest.mark.parametrize("bad", ["ndim", "nghost", "faces", "periodic", "gravity", "r0", "nscalar", "mlp",
+                                 "eos_kind", "eos_fp32", "eos_dual_energy", "eos_R", "eos_mlp"])
 def test_invalid_configurations_are_rejected(bad):
     pr = P.random_periodic(n=(6, 5, 4), ndim=3, nscalar=1)
     if bad == "ndim":
@@ -66,7 +67,19 @@ def test_invalid_configurations_are_rejected(bad):
         pr = pr.with_(nscalar=5)
     elif bad == "mlp":
         pr = pr.with_(limiter="mlp", ng=2)
+    elif bad == "eos_kind":
+        pr = P.with_gas_rad(pr)
+    elif bad == "eos_fp32":
+        pr = P.with_gas_rad(pr).with_(precision="fp32")
+    elif bad == "eos_dual_energy":
+        pr = P.with_internal_energy(P.with_gas_rad(pr))
+    elif bad == "eos_R":
+        pr = P.with_gas_rad(pr).with_(eos_R=0.0)
+    elif bad == "eos_mlp":
+        pr = P.with_gas_rad(pr).with_(limiter="mlp", ng=3, precision="fp32")
     L = H.load_library()
     c, keep = H.make_config(pr)
+    if bad == "eos_kind":
+        c.eos = 2
     assert L.hx_workspace_bytes(C.byref(c)) == 0
     assert len(L.hx_last_error()) > 0
