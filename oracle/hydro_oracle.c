@@ -5,7 +5,8 @@
  * The step follows the paper's order (Sect. 3.2):
  *   1. boundary images of the conserved state (periodic / null-gradient /
  *      reflective, Sect. 3.2 last paragraph);
- *   2. primitives (rho, u, P, f) from the ideal-gas EoS (Sect. 2.3, eq. eos_gas);
+ *   2. primitives (rho, u, P, f) from the ideal-gas EoS (Sect. 2.3, eq. eos_gas) or the gas +
+ *      radiation EoS (eqs. eos_gp_rad_ein, eos_gp_rad);
  *   3. limited slopes of the primitives and the reconstructed face values
  *      W_i -/+ (dr_i/2) sigma  (Sect. 3.2, first equation);
  *   4. the Hancock half step U^{n+1/2}_{L,R} = U_{L,R} + dt/(2 dr_i) [F(U_L) - F(U_R)],
@@ -14,7 +15,8 @@
  *   6. the Godunov update (eq. godunov) in the finite-volume form
  *      U_new = U + dt/dV (F_L dS_L - F_R dS_R) of Sect. 3.3, plus gravity
  *      (Sect. 2.2) and, in spherical coordinates, the momentum source terms of
- *      Sect. 3.1.2 (eq. source_terms_1 and its theta counterpart).
+ *      Sect. 3.1.2 (eq. source_terms_1 and its theta counterpart), 56Ni decay heating
+ *      (Sect. 2.1, eq. heating_ni) and the internal-energy monitor (Sect. 2.4).
  *
  * Readings where the paper is silent are stated at the point of use.
  */
@@ -592,7 +594,24 @@ static int ctx_init(Ctx *x, const or_config *c)
         return OR_EINVAL;
     if (c->eos == OR_EOS_GAS_RAD && (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0) || c->dual_energy))
         return OR_EINVAL;
+    if (c->ni_heating) {
+        if (c->ni_scalar < 0 || c->ni_scalar >= c->nscalar || !(c->ni_tau[0] > 0.0) ||
+            !(c->ni_tau[1] > c->ni_tau[0]) || !(c->ni_m > 0.0) || !(c->ni_Q[0] >= 0.0) || !(c->ni_Q[1] >= 0.0) ||
+            !isfinite(c->time))
+            return OR_EINVAL;
+    }
     return OR_OK;
+}
+
+/* ---- 56Ni decay heating (Sect. 2.1, eq. heating_ni): the energy source rho f_Ni times
+ * lambda {[Q_Ni (tau_Co / tau_Ni - 1) - Q_Co] exp(-t / tau_Ni) + Q_Co exp(-t / tau_Co)},
+ * lambda = 1 / (56 m_u (tau_Co - tau_Ni)), absorbed locally.  The rate per unit mass of 56Ni: */
+double or_ni_rate(const or_config *c, double t)
+{
+    const double tn = c->ni_tau[0], tc = c->ni_tau[1];
+    const double qn = c->ni_Q[0], qc = c->ni_Q[1];
+    const double lam = 1.0 / (c->ni_m * (tc - tn));
+    return lam * ((qn * (tc / tn - 1.0) - qc) * exp(-t / tn) + qc * exp(-t / tc));
 }
 
 /* radial gravity per interior shell; with the monopole term, the enclosed mass is
@@ -783,6 +802,9 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
     st = gravity_setup(&x, U);
     if (st)
         return st;
+    /* decay heating rates at the start and the middle of the step */
+    const double h_n = c->ni_heating ? or_ni_rate(c, c->time) : 0.0;
+    const double h_half = c->ni_heating ? or_ni_rate(c, c->time + 0.5 * dt) : 0.0;
 
     const int s = c->limiter == OR_LIM_MLP ? 3 : 2;
     Box bw, bp, bo;
@@ -879,6 +901,14 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                     grav_source(&x, q, g, S);
                     for (int v = 0; v < nv; v++)
                         du[v] += 0.5 * dt * S[v];
+                }
+                /* decay heating of the state at t^n over the half step; it heats the gas, so the
+                 * monitored internal energy takes it too (reading) */
+                if (c->ni_heating) {
+                    const double sh = h_n * q[5 + c->ni_scalar];
+                    du[4] += 0.5 * dt * sh;
+                    if (c->dual_energy)
+                        du[nv - 1] += 0.5 * dt * sh;
                 }
                 /* positivity fallback (reading; not in the paper): a cell whose half-step face
                  * states are not physical is advanced at first order (zero slopes, no half step) */
@@ -1027,6 +1057,15 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                     S[1] = S[1] + 0.5 * (Xt + Xp) * grg;
                     S[2] = S[2] + (Trt + Xp * gtg);
                     S[3] = S[3] + (Trp + Tt);
+                    have_src = 1;
+                }
+                /* decay heating of the half-step state at t^n + dt/2 (reading: the midpoint in time,
+                 * like the other sources) */
+                if (c->ni_heating) {
+                    const double sh = h_half * uh[5 + c->ni_scalar];
+                    S[4] = S[4] + sh;
+                    if (c->dual_energy)
+                        S[nv - 1] = S[nv - 1] + sh;
                     have_src = 1;
                 }
                 if (have_src)

@@ -8,8 +8,9 @@
  * library.
  *
  * Units of the paper followed here:
- *   Sect. 2.1 (eqs. continuity, momentum, energy, passive scalar), Sect. 2.2
- *   (uniform / point / enclosed-mass gravity), Sect. 2.3 (ideal-gas EoS),
+ *   Sect. 2.1 (eqs. continuity, momentum, energy, passive scalar; 56Ni decay heating,
+ *   eq. heating_ni), Sect. 2.2 (uniform / point / enclosed-mass gravity), Sect. 2.3 (ideal-gas
+ *   and gas + radiation EoS), Sect. 2.4 (internal-energy monitor),
  *   Sect. 3.1.1 (mesh, dS, dV), Sect. 3.1.2 (spherical momentum sources,
  *   eq. source_terms_1 and the theta counterpart), Sect. 3.2 (slope-limited
  *   reconstruction, Hancock half step, Godunov update eq. godunov, HLL/HLLC,
@@ -20,7 +21,11 @@
  * weak waves; the whole step against the exact Sod solution (convergence), first-order Godunov by
  * brute force, conservation, free stream, mirror/permutation symmetry, 1D data in 3D, free fall
  * under uniform gravity, a static spherical wedge, discrete angular momentum, the closed-form
- * enclosed mass and the Sedov-Taylor shock radius; the MLP against torch and finite differences.
+ * enclosed mass and the Sedov-Taylor shock radius; the MLP against torch and finite differences;
+ * the internal-energy monitor's blend branches and second-order agreement with the total energy;
+ * the gas + radiation EoS against round trips, its limits and the isentropic sound speed; the
+ * 56Ni heating rate against the decay chain's populations, its total release and second-order
+ * convergence of a heated flow.
  */
 #ifndef HYDRO_ORACLE_H
 #define HYDRO_ORACLE_H
@@ -62,6 +67,13 @@ typedef struct {
                                  eos_gp_rad, cs_gp_rad; not with dual_energy) */
     double eos_R;             /* gas + radiation: specific gas constant k_b / (mu m_u) */
     double eos_arad;          /* gas + radiation: radiation constant a_r */
+    int ni_heating;           /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.1, eq. heating_ni)
+                                 added to E (and to e with dual_energy) */
+    int ni_scalar;            /* the passive scalar that carries rho f_Ni (0 .. nscalar-1) */
+    double ni_Q[2];           /* energy released per decay of 56Ni and of 56Co */
+    double ni_tau[2];         /* lifetimes tau_Ni < tau_Co */
+    double ni_m;              /* mass of one 56Ni nucleus (56 m_u) */
+    double time;              /* time t^n at the start of the step (the decay clock) */
 } or_config;
 
 /* Full step of interior U (layout [nvar][n3][n2][n1]) with time step dt into Unew.
@@ -89,6 +101,9 @@ double or_eos_state(const or_config *c, double rho, double e, double *P, double 
 
 /* Internal energy per unit volume of density rho and pressure P (Sect. 2.3). */
 double or_eos_energy(const or_config *c, double rho, double P);
+
+/* 56Ni decay heating rate per unit mass of 56Ni at time t (eq. heating_ni without rho f_Ni). */
+double or_ni_rate(const or_config *c, double t);
 
 /* Blend factor alpha of the internal-energy monitor (Sect. 2.4) for internal energy e and kinetic
  * energy e_k (per unit volume) and the criterion eps. */

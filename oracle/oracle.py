@@ -35,6 +35,8 @@ class OrConfig(C.Structure):
         ("gravity", C.c_int), ("g0", C.c_double * 3), ("G", C.c_double), ("Mc", C.c_double),
         ("mlp", _DP), ("dual_energy", C.c_int), ("de_eps", C.c_double),
         ("eos", C.c_int), ("eos_R", C.c_double), ("eos_arad", C.c_double),
+        ("ni_heating", C.c_int), ("ni_scalar", C.c_int), ("ni_Q", C.c_double * 2), ("ni_tau", C.c_double * 2),
+        ("ni_m", C.c_double), ("time", C.c_double),
     ]
 
 
@@ -65,6 +67,8 @@ def lib(path: str = LIB_PATH):
         L.or_eos_state.restype = C.c_double
         L.or_eos_energy.argtypes = [C.POINTER(OrConfig), C.c_double, C.c_double]
         L.or_eos_energy.restype = C.c_double
+        L.or_ni_rate.argtypes = [C.POINTER(OrConfig), C.c_double]
+        L.or_ni_rate.restype = C.c_double
         L.or_de_alpha.argtypes = [C.c_double, C.c_double, C.c_double]
         L.or_de_alpha.restype = C.c_double
         L.or_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
@@ -133,6 +137,12 @@ class Oracle:
         c.eos = EOS[_opt(prob, "eos", "gas")]
         c.eos_R = float(_opt(prob, "eos_R", 0.0))
         c.eos_arad = float(_opt(prob, "eos_arad", 0.0))
+        c.ni_heating = 1 if _opt(prob, "ni_heating", False) else 0
+        c.ni_scalar = int(_opt(prob, "ni_scalar", 0))
+        for i in range(2):
+            c.ni_Q[i] = float(_opt(prob, "ni_Q", (0.0, 0.0))[i])
+            c.ni_tau[i] = float(_opt(prob, "ni_tau", (1.0, 2.0))[i])
+        c.ni_m = float(_opt(prob, "ni_m", 1.0))
         c.de_eps = float(getattr(prob, "de_eps", 1e-6)) if not isinstance(prob, dict) else float(prob.get("de_eps", 1e-6))
         self._mlp = None
         if mlp_weights is not None:
@@ -155,8 +165,10 @@ class Oracle:
     def shape(self):
         return (self.nvar, self.n[2], self.n[1], self.n[0])
 
-    def step(self, U: np.ndarray, dt: float) -> tuple[np.ndarray, int]:
+    def step(self, U: np.ndarray, dt: float, t: float = 0.0) -> tuple[np.ndarray, int]:
+        """One step from time t (the decay clock of the 56Ni heating; unused otherwise)."""
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
+        self.cfg.time = float(t)
         out = np.empty_like(U)
         st = self._L.or_step(self._cfgp(), _ptr(U), float(dt), _ptr(out))
         if st == EINVAL:
@@ -165,8 +177,9 @@ class Oracle:
             raise MemoryError("oracle: out of memory")
         return out, st
 
-    def step_box(self, U: np.ndarray, dt: float, lo, hi) -> tuple[np.ndarray, int]:
+    def step_box(self, U: np.ndarray, dt: float, lo, hi, t: float = 0.0) -> tuple[np.ndarray, int]:
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
+        self.cfg.time = float(t)
         lo3 = (C.c_int * 3)(*[int(v) for v in lo])
         hi3 = (C.c_int * 3)(*[int(v) for v in hi])
         ext = [int(hi[d]) - int(lo[d]) for d in range(3)]
@@ -230,6 +243,10 @@ class Oracle:
         P, cs = C.c_double(), C.c_double()
         T = self._L.or_eos_state(self._cfgp(), float(rho), float(e), C.byref(P), C.byref(cs))
         return T, P.value, cs.value
+
+    def ni_rate(self, t: float) -> float:
+        """56Ni decay heating per unit mass of 56Ni at time t (eq. heating_ni)."""
+        return self._L.or_ni_rate(self._cfgp(), float(t))
 
     def eos_energy(self, rho: float, P: float) -> float:
         return self._L.or_eos_energy(self._cfgp(), float(rho), float(P))

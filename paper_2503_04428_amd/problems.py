@@ -58,6 +58,11 @@ class Problem:
     eos: str = "gas"              # "gas" (eq. eos_gas) or "gas_rad" (gas + radiation, Sect. 2.3)
     eos_R: float = 0.0            # gas + radiation: specific gas constant k_b / (mu m_u)
     eos_arad: float = 0.0         # gas + radiation: radiation constant
+    ni_heating: bool = False      # 56Ni decay heating (Sect. 2.1, eq. heating_ni)
+    ni_scalar: int = 0            # the passive scalar carrying rho f_Ni
+    ni_Q: tuple = (0.0, 0.0)      # energy per decay of 56Ni and 56Co
+    ni_tau: tuple = (1.0, 2.0)    # lifetimes of 56Ni and 56Co
+    ni_m: float = 1.0             # mass of a 56Ni nucleus (56 m_u)
 
     @property
     def nvar(self) -> int:
@@ -591,3 +596,34 @@ def rad_wall1d(n: int = 400, u0: float = -3.0, R: float = 1.0, arad: float = 30.
                    nscalar=0, gamma=g, cfl=0.5, riemann="hllc", limiter="vanleer",
                    bc=[["reflective", "transmissive"], ["periodic"] * 2, ["periodic"] * 2], U0=U,
                    eos="gas_rad", eos_R=R, eos_arad=arad)
+
+
+# 56Ni -> 56Co -> 56Fe in CGS: energies per decay (1.75 and 3.73 MeV, gamma rays and positrons) and
+# lifetimes (8.8 and 111.3 days) as Sect. 2.1 gives them; the mass of a 56Ni nucleus is 56 m_u
+MEV_ERG = 1.602176634e-6
+M_U_G = 1.66053906660e-24
+DAY_S = 86400.0
+NI_CGS = dict(ni_Q=(1.75 * MEV_ERG, 3.73 * MEV_ERG), ni_tau=(8.8 * DAY_S, 111.3 * DAY_S), ni_m=56.0 * M_U_G)
+
+
+def with_ni_heating(prob: Problem, scalar: int = 0, Q=(1.0, 2.0), tau=(0.05, 0.6), m: float = 1.0) -> Problem:
+    """The same problem with 56Ni decay heating (Sect. 2.1, eq. heating_ni): passive scalar `scalar`
+    carries rho f_Ni.  The defaults are code units in which the decay is fast enough to matter in a
+    short run; NI_CGS holds the physical constants."""
+    return prob.with_(name=prob.name + "+ni", ni_heating=True, ni_scalar=int(scalar), ni_Q=tuple(Q),
+                      ni_tau=tuple(tau), ni_m=float(m))
+
+
+def ni_blob3d(n=(24, 20, 16), seed: int = 61, eos: str = "gas") -> Problem:
+    """Random periodic 3D flow with a 56Ni-rich blob (scalar 0 = rho f_Ni, f_Ni up to 0.8 in a
+    Gaussian blob, 0.05 outside; scalar 1 an ordinary tracer), with decay heating in code units."""
+    base = random_periodic(n=n, ndim=3, nscalar=2, seed=seed)
+    U = base.U0.copy()
+    x = [centers(base.faces[d], base.ng, n[d]) for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    c = [0.5 * (x[d][0] + x[d][-1]) for d in range(3)]
+    r2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+    f = 0.05 + 0.75 * np.exp(-r2 / 0.02)
+    U[5] = U[0] * f
+    pr = with_ni_heating(base.with_(U0=U, name="ni_blob"))
+    return with_gas_rad(pr) if eos == "gas_rad" else pr
