@@ -92,6 +92,16 @@ typedef struct {
                                internal-energy monitor and a limiter other than the learned one */
     double eos_R;           /* HX_EOS_GAS_RAD: specific gas constant k_b/(mu m_u), > 0 */
     double eos_arad;        /* HX_EOS_GAS_RAD: radiation constant a, >= 0 */
+    int ni_heating;         /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.1, eq. heating_ni):
+                               E (and e with dual_energy) gains rho f_Ni h(t) with
+                               h = lambda {[Q_Ni (tau_Co/tau_Ni - 1) - Q_Co] exp(-t/tau_Ni)
+                               + Q_Co exp(-t/tau_Co)}, lambda = 1/(ni_m (tau_Co - tau_Ni)), taken at
+                               the step's start in the half step and at its midpoint in the update;
+                               t is the context's decay clock (hx_set_time).  Needs FP64.  0: off */
+    int ni_scalar;          /* the passive scalar (0 .. nscalar-1) that carries rho f_Ni */
+    double ni_Q[2];         /* energy released per decay of 56Ni and of 56Co, >= 0 */
+    double ni_tau[2];       /* lifetimes of 56Ni and 56Co, 0 < tau_Ni < tau_Co */
+    double ni_m;            /* mass of one 56Ni nucleus (56 m_u in the caller's units), > 0 */
 } hx_config;
 
 /* Device bytes the caller must provide to hx_create for this configuration, or 0 if the
@@ -146,6 +156,13 @@ hx_status hx_set_zchunk(hx_ctx *ctx, int kz);
 /* The z planes per workgroup in use: the value set, else the automatic choice (0 before the first
  * 3D step).  HX_EINVAL for null arguments. */
 hx_status hx_get_zchunk(hx_ctx *ctx, int *kz);
+
+/* The decay clock of the 56Ni heating: with ni_heating on, every step advances it by its dt on the
+ * device (also with hx_step_device); without, steps leave it alone.  hx_create starts it at 0.
+ * hx_set_time sets it (asynchronous); hx_get_time synchronises and reads it.  HX_EINVAL for null
+ * arguments or a non-finite t. */
+hx_status hx_set_time(hx_ctx *ctx, double t);
+hx_status hx_get_time(hx_ctx *ctx, double *t);
 
 /* Enclosed-mass table of the last step that used HX_GRAVITY_POINT_MONOPOLE (n[0] doubles to the
  * host; synchronises).  For tests of the enclosed-mass reduction. */

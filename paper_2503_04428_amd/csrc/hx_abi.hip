@@ -72,7 +72,7 @@ struct Layout {
     size_t state[2];
     size_t tab[3][3];  // cm, cp, w per axis
     size_t rabs, sabs, rf, vr, hr, ct, sf;
-    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp;
+    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp, time;
     size_t total;
     int ntab[3];
     int nchunk, nred;
@@ -133,6 +133,19 @@ hx_status validate(const hx_config* c)
             return fail(HX_EINVAL, "the gas + radiation EoS is not built with the learned limiter");
         if (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0) || !std::isfinite(c->eos_R) || !std::isfinite(c->eos_arad))
             return fail(HX_EINVAL, "the gas + radiation EoS needs eos_R > 0 and eos_arad >= 0");
+    }
+    if (c->ni_heating != 0 && c->ni_heating != 1)
+        return fail(HX_EINVAL, "ni_heating must be 0 or 1 (got %d)", c->ni_heating);
+    if (c->ni_heating) {
+        if (c->precision != HX_PRECISION_FP64)
+            return fail(HX_EINVAL, "the 56Ni heating is built for the FP64 form");
+        if (c->ni_scalar < 0 || c->ni_scalar >= c->nscalar)
+            return fail(HX_EINVAL, "ni_scalar %d is not one of the %d passive scalars", c->ni_scalar, c->nscalar);
+        if (!(c->ni_tau[0] > 0.0) || !(c->ni_tau[1] > c->ni_tau[0]) || !std::isfinite(c->ni_tau[1]))
+            return fail(HX_EINVAL, "the 56Ni heating needs 0 < tau_Ni < tau_Co");
+        if (!(c->ni_m > 0.0) || !std::isfinite(c->ni_m) || !(c->ni_Q[0] >= 0.0) || !(c->ni_Q[1] >= 0.0) ||
+            !std::isfinite(c->ni_Q[0]) || !std::isfinite(c->ni_Q[1]))
+            return fail(HX_EINVAL, "the 56Ni heating needs ni_m > 0 and finite Q >= 0");
     }
     if (c->precision != HX_PRECISION_FP64 && c->precision != HX_PRECISION_FP32)
         return fail(HX_EINVAL, "unknown precision %d", c->precision);
@@ -221,11 +234,17 @@ Layout layout(const hx_config* c)
     L.flag = take(sizeof(int));
     L.tot = take(sizeof(double) * nv);
     L.mlp = take(sizeof(float) * HX_MLP_NPARAM);
+    L.time = take(sizeof(double));  // the decay clock of the 56Ni heating
     L.total = off;
     return L;
 }
 
 __global__ void clear_flag_kernel(int* f) { f[0] = 0; }
+
+__global__ void set_time_kernel(double* t, double v) { t[0] = v; }
+
+// t += dt after a heated step, dt from the host or from the device
+__global__ void advance_time_kernel(double* t, double dt, const double* d_dt) { t[0] = t[0] + (d_dt ? d_dt[0] : dt); }
 
 }  // namespace
 
@@ -434,7 +453,15 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     p.de_eps = c.de_eps;
     p.eos_R = c.eos_R;
     p.eos_arad = c.eos_arad;
-    const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC;
+    p.ni = c.ni_heating ? 5 + c.ni_scalar : -1;
+    for (int i = 0; i < 2; i++) {
+        p.ni_Q[i] = c.ni_Q[i];
+        p.ni_tau[i] = c.ni_tau[i];
+    }
+    p.ni_m = c.ni_m;
+    p.t_in = at<double>(x, x->L.time);
+    // the fixed HLLC + van Leer sweeps are built without the 56Ni heating
+    const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC && !c.ni_heating;
     if (c.limiter == HX_LIMITER_MLP && !x->have_mlp)
         return fail(HX_ESTATE, "the learned limiter needs hx_set_mlp before stepping");
     // the instantiation for this configuration; with occ, only its workgroups per compute unit
@@ -468,6 +495,10 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     if (e != hipSuccess)
         return fail(HX_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     x->cur = 1 - x->cur;
+    if (c.ni_heating) {
+        advance_time_kernel<<<1, 1, 0, x->stream>>>(at<double>(x, x->L.time), dt, d_dt);
+        HIPCHECK(hipGetLastError());
+    }
     x->dtpart_valid = true;
     x->dtpart_nb = hx::sweep_nblocks(c.ndim, c.n, p.kz);
     return HX_OK;
@@ -540,12 +571,33 @@ hx_status hx_create(const hx_config* cfg, void* d_workspace, size_t workspace_by
         }
     }
     clear_flag_kernel<<<1, 1, 0, x->stream>>>(at<int>(x, L.flag));
+    set_time_kernel<<<1, 1, 0, x->stream>>>(at<double>(x, L.time), 0.0);
     hipError_t e = hipStreamSynchronize(x->stream);
     if (e != hipSuccess) {
         delete x;
         return fail(HX_EHIP, "create: %s", hipGetErrorString(e));
     }
     *out = x;
+    return HX_OK;
+}
+
+hx_status hx_set_time(hx_ctx* x, double t)
+{
+    if (!x || !std::isfinite(t))
+        return fail(HX_EINVAL, "null context or non-finite time");
+    set_time_kernel<<<1, 1, 0, x->stream>>>(at<double>(x, x->L.time), t);
+    HIPCHECK(hipGetLastError());
+    return HX_OK;
+}
+
+hx_status hx_get_time(hx_ctx* x, double* t)
+{
+    if (!x || !t)
+        return fail(HX_EINVAL, "null argument");
+    double h = 0.0;
+    HIPCHECK(hipMemcpyAsync(&h, at<double>(x, x->L.time), sizeof(double), hipMemcpyDeviceToHost, x->stream));
+    HIPCHECK(hipStreamSynchronize(x->stream));
+    *t = h;
     return HX_OK;
 }
 

@@ -103,6 +103,26 @@ __device__ __forceinline__ double rad_pressure(const Gas<double>& g, double rho,
     return (rho * g.Rg) * T + (g.arad * t4(T)) / 3.0;
 }
 
+// a wave-uniform double moved to scalar registers (it stays live through a whole sweep)
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 56Ni decay heating per unit mass of 56Ni at time t (Sect. 2.1, eq. heating_ni):
+// lambda {[Q_Ni (tau_Co/tau_Ni - 1) - Q_Co] exp(-t/tau_Ni) + Q_Co exp(-t/tau_Co)},
+// lambda = 1 / (m_Ni (tau_Co - tau_Ni))
+__device__ __forceinline__ double ni_rate(const SweepParams& p, double t)
+{
+    const double tn = p.ni_tau[0], tc = p.ni_tau[1];
+    const double qn = p.ni_Q[0], qc = p.ni_Q[1];
+    const double lam = 1.0 / (p.ni_m * (tc - tn));
+    return lam * ((qn * (tc / tn - 1.0) - qc) * exp(-t / tn) + qc * exp(-t / tc));
+}
+
 // sound speed from primitives w, reciprocal density inv and (gas + radiation) temperature T:
 // eq. eos_gas, or eq. cs_gp_rad with alpha = P_r / P_g
 template <typename R, int EOS>

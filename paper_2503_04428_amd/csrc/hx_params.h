@@ -66,6 +66,11 @@ struct SweepParams {
     double de_eps;       // criterion of the internal-energy monitor's blend factor
     double eos_R;        // gas + radiation EoS: specific gas constant and radiation constant
     double eos_arad;
+    int ni;              // 56Ni decay heating: field index (5 + scalar) of rho f_Ni, or -1 (off)
+    double ni_Q[2];      // energy per decay of 56Ni and 56Co
+    double ni_tau[2];    // lifetimes of 56Ni and 56Co
+    double ni_m;         // mass of a 56Ni nucleus
+    const double* t_in;  // the decay clock at the start of the step (advanced after the sweep)
 };
 
 }  // namespace hx

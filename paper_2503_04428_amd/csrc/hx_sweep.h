@@ -218,6 +218,24 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     }
     const double dtd = p.dt_dev ? p.dt_dev[0] : p.dt_host;
     const R dt = N::from_d(dtd);
+    // 56Ni heating rates at the start and the middle of the step (FP64 forms with the run-time
+    // limiter and solver, the internal-energy monitor or the gas + radiation EoS)
+    const bool heat = sizeof(R) == 8 && SPEC != 1 && p.ni >= 0;
+    double h_n = 0.0, h_half = 0.0;
+    if (heat) {
+        const double t = p.t_in[0];
+        h_n = uniform_d(ni_rate(p, t));
+        h_half = uniform_d(ni_rate(p, t + 0.5 * dtd));
+    }
+    // rho f_Ni of a state (the field index is a run-time value: select, not index, registers)
+    auto ni_of = [&](const R* q) {
+        double f = 0.0;
+#pragma unroll
+        for (int v = 5; v < NV - DE; v++)
+            if (v == p.ni)
+                f = (double)q[v];
+        return f;
+    };
     Gas<R> gas;
     gas.gamma = N::from_d(p.gamma);
     gas.gm1 = N::from_d(p.gamma - 1.0);
@@ -702,6 +720,14 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             for (int v = 5; v < NV; v++)
                 du[v] += hs * R(0);
         }
+        // 56Ni decay heating of U^n at t^n over the half step (the monitored e takes it too)
+        if (heat) {
+            const R hs = R(0.5) * dt;
+            const R sh = N::from_d(h_n * ni_of(qcur));
+            du[4] += hs * sh;
+            if constexpr (DE)
+                du[NV - 1] += hs * sh;
+        }
         // positivity of all half-step face states; otherwise first order for this cell
         bool bad = false;
         if constexpr (RESLOPE)
@@ -829,6 +855,14 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 Sg[3] = (double)u[0] * g[2];
                 Sg[4] = (double)u[1] * g[0] + (double)u[2] * g[1] + (double)u[3] * g[2];
             }
+            // 56Ni decay heating of the half-step state at t^n + dt/2; Sg[0] keeps the share of
+            // the monitored internal energy
+            if (heat) {
+                const double sh = h_half * ni_of(u);
+                Sg[4] = Sg[4] + sh;
+                if constexpr (DE)
+                    Sg[0] = sh;
+            }
             if constexpr (GEOM == HX_SPH) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -872,7 +906,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     if constexpr (DE)
                         acc[NV - 1] += kv * (pe_prev * (ufzlo * dS - ufz * dS));
                 }
-                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
+                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH || heat) {
                     double S[5] = {0.0, sg[1], sg[2], sg[3], sg[4]};
                     if (GEOM == HX_SPH) {
                         const double Xp = 0.5 * ((double)fzlo[3] + (double)Fz[3]);
@@ -884,8 +918,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     for (int v = 1; v < 5; v++)
                         acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
                 }
-                if constexpr (DE)
+                if constexpr (DE) {
+                    if (heat)
+                        acc[NV - 1] = acc[NV - 1] + dtd * sg[0];
                     de_blend(acc, en_prev, alpha_prev);
+                }
                 const long long off = ((long long)kp * n1 + jj) * n0 + ii;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -1061,14 +1098,19 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 1; v < 5; v++)
                     sg[v] = S[v];
+                if constexpr (DE)
+                    sg[0] = Sg[0];
             } else {
-                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH) {
+                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH || heat) {
 #pragma unroll
                     for (int v = 1; v < 5; v++)
                         acc[v] = N::from_d((double)acc[v] + dtd * S[v]);
                 }
-                if constexpr (DE)
+                if constexpr (DE) {
+                    if (heat)
+                        acc[NV - 1] = acc[NV - 1] + dtd * Sg[0];
                     de_blend(acc, enk, alphak);
+                }
                 const long long off = ((long long)jj * n0) + ii;
 #pragma unroll
                 for (int v = 0; v < NV; v++)

@@ -37,6 +37,8 @@ class HxConfig(C.Structure):
         ("bc", (C.c_int * 2) * 3), ("gravity", C.c_int), ("g0", C.c_double * 3),
         ("G", C.c_double), ("Mc", C.c_double), ("dual_energy", C.c_int), ("de_eps", C.c_double),
         ("eos", C.c_int), ("eos_R", C.c_double), ("eos_arad", C.c_double),
+        ("ni_heating", C.c_int), ("ni_scalar", C.c_int), ("ni_Q", C.c_double * 2), ("ni_tau", C.c_double * 2),
+        ("ni_m", C.c_double),
     ]
 
 
@@ -55,7 +57,7 @@ _lib = None
 # names of the exported entry points, as declared in include/hydro.h
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
            "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
-           "hx_set_zchunk", "hx_get_zchunk", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
+           "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
            "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_adam", "hx_last_error", "hx_destroy"]
 
 
@@ -84,6 +86,8 @@ def load_library():
     L.hx_set_mlp.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
     L.hx_set_zchunk.argtypes = [vp, C.c_int]
     L.hx_get_zchunk.argtypes = [vp, C.POINTER(C.c_int)]
+    L.hx_set_time.argtypes = [vp, C.c_double]
+    L.hx_get_time.argtypes = [vp, C.POINTER(C.c_double)]
     L.hx_enclosed_mass.argtypes = [vp, _DP]
     L.hx_mlp_eval.argtypes = [vp, vp, C.c_longlong, vp, vp]
     L.hx_mlp_features.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, vp]
@@ -138,6 +142,12 @@ def make_config(prob, precision: str | None = None):
     c.eos = EOS[_opt(prob, "eos", "gas")]
     c.eos_R = float(_opt(prob, "eos_R", 0.0))
     c.eos_arad = float(_opt(prob, "eos_arad", 0.0))
+    c.ni_heating = 1 if _opt(prob, "ni_heating", False) else 0
+    c.ni_scalar = int(_opt(prob, "ni_scalar", 0))
+    for i in range(2):
+        c.ni_Q[i] = float(_opt(prob, "ni_Q", (0.0, 0.0))[i])
+        c.ni_tau[i] = float(_opt(prob, "ni_tau", (1.0, 2.0))[i])
+    c.ni_m = float(_opt(prob, "ni_m", 1.0))
     return c, faces
 
 
@@ -268,6 +278,15 @@ class Solver:
         """z planes per workgroup in use (0 before the first automatic 3D step)."""
         v = C.c_int(0)
         self._call(self.L.hx_get_zchunk(self.ctx, C.byref(v)))
+        return v.value
+
+    def set_time(self, t: float):
+        """Set the decay clock of the 56Ni heating (every step advances it by its dt)."""
+        self._call(self.L.hx_set_time(self.ctx, float(t)))
+
+    def time(self) -> float:
+        v = C.c_double(0.0)
+        self._call(self.L.hx_get_time(self.ctx, C.byref(v)))
         return v.value
 
     def enclosed_mass(self) -> np.ndarray:
