@@ -302,6 +302,16 @@ static void cons(const Ctx *x, const double *w, double *q)
         q[x->nvar - 1] = w[x->nvar - 1];
 }
 
+/* pressure of density rho and internal energy e per unit volume (the internal-energy monitor's
+ * P for its -P div(u) term): (gamma - 1) e, or from the temperature of the gas + radiation EoS */
+static double pressure_from_e(const Ctx *x, double rho, double e)
+{
+    if (x->eos != OR_EOS_GAS_RAD)
+        return x->gm1 * e;
+    const double T = temp_from_e(x, rho, e);
+    return (rho * x->R) * T + (x->arad * t4(T)) / 3.0;
+}
+
 static double pressure_of(const Ctx *x, const double *q)
 {
     double w[MAXV];
@@ -592,7 +602,7 @@ static int ctx_init(Ctx *x, const or_config *c)
     x->arad = c->eos_arad;
     if (c->eos != OR_EOS_GAS && c->eos != OR_EOS_GAS_RAD)
         return OR_EINVAL;
-    if (c->eos == OR_EOS_GAS_RAD && (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0) || c->dual_energy))
+    if (c->eos == OR_EOS_GAS_RAD && (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0)))
         return OR_EINVAL;
     if (c->ni_heating) {
         if (c->ni_scalar < 0 || c->ni_scalar >= c->nscalar || !(c->ni_tau[0] > 0.0) ||
@@ -891,9 +901,10 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                     for (int v = 0; v < nv; v++)
                         du[v] += lam * (fm[v] - fp[v]);
                     /* internal energy: - (dt/2) P div(u) with the reconstructed face velocities
-                     * and P = (gamma - 1) e of the cell (eq. pressure_fix; reading) */
+                     * and the pressure of the cell's e ((gamma - 1) e, or through the gas + radiation
+                     * EoS; eq. pressure_fix; reading) */
                     if (c->dual_energy)
-                        du[nv - 1] += lam * ((x.gm1 * q[nv - 1]) * (wm[1 + d] - wp[1 + d]));
+                        du[nv - 1] += lam * (pressure_from_e(&x, q[0], q[nv - 1]) * (wm[1 + d] - wp[1 + d]));
                 }
                 if (c->gravity != OR_GRAV_NONE) {
                     double g[3], S[MAXV];
@@ -960,7 +971,8 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                 double acc[MAXV], Fm[3][MAXV], Fp[3][MAXV];
                 double ufm = 0.0, ufp = 0.0;  /* interface velocities (internal energy) */
                 /* P of the cell's half-step internal energy, like the other sources (reading) */
-                const double pe = c->dual_energy ? x.gm1 * UH[(nv - 1) * np + ip] : 0.0;
+                const double pe =
+                    c->dual_energy ? pressure_from_e(&x, UH[0 * np + ip], UH[(nv - 1) * np + ip]) : 0.0;
                 for (int v = 0; v < nv; v++)
                     acc[v] = Q[v * nw + iw];
                 for (int d = 0; d < 3; d++) {

@@ -64,7 +64,7 @@ typedef struct {
                                  eq. pressure_fix); needs HLLC */
     double de_eps;            /* the criterion epsilon of the blend factor alpha (paper: 1e-6) */
     int eos;                  /* OR_EOS_GAS (eq. eos_gas) or OR_EOS_GAS_RAD (eqs. eos_gp_rad_ein,
-                                 eos_gp_rad, cs_gp_rad; not with dual_energy) */
+                                 eos_gp_rad, cs_gp_rad) */
     double eos_R;             /* gas + radiation: specific gas constant k_b / (mu m_u) */
     double eos_arad;          /* gas + radiation: radiation constant a_r */
     int ni_heating;           /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.1, eq. heating_ni)

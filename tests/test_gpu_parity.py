@@ -330,3 +330,37 @@ def test_fp32_form_accuracy_sod_and_sedov(H):
     rel = np.abs(Ug - Uo).reshape(7, -1).mean(axis=1) / np.maximum(np.abs(Uo).reshape(7, -1).mean(axis=1), 1e-300)
     print("Sedov 32^3 100 steps, fp32 form L1 relative error per field:", rel)
     assert np.all(rel[[0, 4, 5, 6]] < 1e-4)
+
+
+def test_fp64_parity_beyond_32bit_offsets(H):
+    """A 704^3 random state with 7 fields (2.44e9 values per state, beyond 32-bit element offsets;
+    19.5 GB per FP64 state): the first step on sampled boxes, including the far corner whose last
+    field sits above 2^31 elements, against the oracle.  The time step is fixed (the signal speed
+    is below 5 cells per unit time here), so the oracle only evaluates the boxes."""
+    import torch
+    n = 704
+    prob = P.random_periodic(n=(n, n, n), ndim=3, nscalar=2, seed=71)
+    assert prob.nvar * prob.ncells > 2 ** 31
+    announce("fp64 704^3 random periodic first step (64-bit offsets)")
+    o = O.Oracle(prob)
+    U0 = prob.U0
+    dt = 0.05 / n
+    s = H.Solver(prob)
+    s.set_state(U0)
+    s.step(dt)
+    G = s.get_state()
+    s.stream.synchronize()
+    rng = np.random.default_rng(3)
+    boxes = [((n - 4, n - 4, n - 4), (n, n, n)), ((0, 0, 0), (4, 4, 4)), ((0, n - 3, n - 5), (5, n, n)),
+             ((348, 350, 352), (353, 355, 357))]
+    for _ in range(4):
+        lo = rng.integers(0, n - 4, size=3)
+        boxes.append((tuple(int(v) for v in lo), tuple(int(v) + 4 for v in lo)))
+    for lo, hi in boxes:
+        ob, st = o.step_box(U0, dt, lo, hi)
+        assert st == 0
+        gb = G[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        assert_parity(gb, ob, what=f"704^3 box {lo}-{hi}")
+    del G
+    s.close()
+    torch.cuda.empty_cache()
