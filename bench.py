@@ -194,10 +194,12 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the Sedov cube")
-    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod", "boosted", "rad"],
+    ap.add_argument("--workload", default="sedov", choices=["sedov", "rt", "wedge", "sod", "boosted", "rad", "sn"],
                     help="sedov (default, the headline line); rt, wedge, sod, boosted (Sedov in a moving "
                          "medium with the internal-energy monitor, FP64), rad (Sedov with the gas + "
-                         "radiation EoS, FP64) measure the other workloads")
+                         "radiation EoS, FP64), sn (spherical wedge in the paper's SN configuration: "
+                         "gas + radiation EoS, monitor, 56Ni heating, point mass, hybrid grid; FP64) "
+                         "measure the other workloads")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
@@ -237,6 +239,11 @@ def main():
         prob = problems.with_gas_rad(problems.sedov3d(n=args.n))
         wl = (f"sedov3d-{args.n}^3 with the gas + radiation EoS (R 1, a 30; 7 fields, HLLC, van Leer, "
               f"CFL 0.5)")
+        args.forms = "fp64"
+    elif args.workload == "sn":
+        prob = problems.sn_wedge3d(n_lin=256, n_log=256, nth=128, nph=128)
+        wl = ("sn-wedge 512x128x128 spherical (hybrid linear-log r, gas + radiation EoS, internal-energy "
+              "monitor, 56Ni heating, point mass, minmod, HLLC; 8 fields)")
         args.forms = "fp64"
     elif args.workload == "rt":
         prob = problems.rt3d()

@@ -88,8 +88,9 @@ typedef struct {
                                radiation (Sect. 2.3, eqs. eos_gp_rad_ein and eos_gp_rad:
                                e = rho R T/(gamma-1) + a T^4, P = rho R T + a T^4/3; T from e or P by
                                ten Newton steps from the smaller of the gas-only and radiation-only
-                               temperatures; sound speed of eq. cs_gp_rad); needs FP64, no
-                               internal-energy monitor and a limiter other than the learned one */
+                               temperatures; sound speed of eq. cs_gp_rad; with dual_energy the
+                               monitor's P is the EoS pressure of (rho, e)); needs FP64 and a
+                               limiter other than the learned one */
     double eos_R;           /* HX_EOS_GAS_RAD: specific gas constant k_b/(mu m_u), > 0 */
     double eos_arad;        /* HX_EOS_GAS_RAD: radiation constant a, >= 0 */
     int ni_heating;         /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.1, eq. heating_ni):

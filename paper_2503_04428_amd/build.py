@@ -5,7 +5,8 @@ Each HIP translation unit is compiled separately (no relocatable device code):
   hx_sweep_fp32*.hip FP32-form sweep (contraction allowed)
   (the *_hllc_vl units fix HLLC + van Leer at compile time; the others take them at run time;
    hx_sweep_fp32_mlp.hip is the learned-limiter form, hx_sweep_fp64_de.hip the FP64 sweep with the
-   internal-energy monitor, hx_sweep_fp64_rad.hip the FP64 sweep with the gas + radiation EoS)
+   internal-energy monitor, hx_sweep_fp64_rad.hip the FP64 sweep with the gas + radiation EoS,
+   hx_sweep_fp64_de_rad.hip both)
   hx_reduce.hip      dt / totals / enclosed-mass reductions, -ffp-contract=off
   hx_mlp.hip         learned limiter: BF16-MFMA evaluation, training samples, FP32 training
   hx_abi.hip         C ABI host code
@@ -34,6 +35,7 @@ UNITS = {
     "hx_sweep_fp64_hllc_vl.hip": ["-ffp-contract=off"],
     "hx_sweep_fp64_de.hip": ["-ffp-contract=off"],
     "hx_sweep_fp64_rad.hip": ["-ffp-contract=off"],
+    "hx_sweep_fp64_de_rad.hip": ["-ffp-contract=off"],
     "hx_sweep_fp32.hip": [],
     "hx_sweep_fp32_hllc_vl.hip": [],
     "hx_sweep_fp32_mlp.hip": [],

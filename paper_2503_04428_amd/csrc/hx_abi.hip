@@ -127,8 +127,6 @@ hx_status validate(const hx_config* c)
     if (c->eos == HX_EOS_GAS_RAD) {
         if (c->precision != HX_PRECISION_FP64)
             return fail(HX_EINVAL, "the gas + radiation EoS is built for the FP64 form");
-        if (c->dual_energy)
-            return fail(HX_EINVAL, "the gas + radiation EoS is not built with the internal-energy monitor");
         if (c->limiter == HX_LIMITER_MLP)
             return fail(HX_EINVAL, "the gas + radiation EoS is not built with the learned limiter");
         if (!(c->eos_R > 0.0) || !(c->eos_arad >= 0.0) || !std::isfinite(c->eos_R) || !std::isfinite(c->eos_arad))
@@ -467,7 +465,8 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     // the instantiation for this configuration; with occ, only its workgroups per compute unit
     auto sweep = [&](int* occ) -> hipError_t {
         if (c.dual_energy)
-            return hx::launch_sweep_fp64_de(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+            return c.eos == HX_EOS_GAS_RAD ? hx::launch_sweep_fp64_de_rad(p, c.ndim, x->nvar, c.geom, x->stream, occ)
+                                           : hx::launch_sweep_fp64_de(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (c.eos == HX_EOS_GAS_RAD)
             return hx::launch_sweep_fp64_rad(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (c.limiter == HX_LIMITER_MLP)

@@ -216,7 +216,7 @@ __device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w, R* T = n
 
 // gas + radiation EoS: primitives of two conserved states (the faces of one Riemann problem) with
 // their two temperature solves in one loop; the same values as two calls of to_prim
-template <int NV>
+template <int NV, bool DE = false>
 __device__ __forceinline__ void to_prim_rad2(const Gas<double>& g, const double* qa, const double* qb, double* wa,
                                              double* wb, double& ia, double& ib, double& Ta, double& Tb)
 {
@@ -235,8 +235,10 @@ __device__ __forceinline__ void to_prim_rad2(const Gas<double>& g, const double*
         w[j][3] = u3;
         e[j] = q[j][4] - ke;
 #pragma unroll
-        for (int v = 5; v < NV; v++)
+        for (int v = 5; v < NV - DE; v++)
             w[j][v] = q[j][v] * inv[j];
+        if (DE)
+            w[j][NV - 1] = q[j][NV - 1];
     }
     temp_solve<false, 2>(g, rho, e, T);
 #pragma unroll
@@ -301,7 +303,7 @@ __device__ __forceinline__ void to_cons(const Gas<R>& g, const R* w, R* q)
 
 // gas + radiation EoS: conserved state of primitives w whose internal energy e(rho, P) is already
 // known (rad_energy2); the same values as to_cons
-template <int NV>
+template <int NV, bool DE = false>
 __device__ __forceinline__ void to_cons_e(const double* w, double e, double* q)
 {
     const double rho = w[0];
@@ -311,8 +313,10 @@ __device__ __forceinline__ void to_cons_e(const double* w, double e, double* q)
     q[3] = rho * w[3];
     q[4] = e + 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
 #pragma unroll
-    for (int v = 5; v < NV; v++)
+    for (int v = 5; v < NV - DE; v++)
         q[v] = rho * w[v];
+    if (DE)
+        q[NV - 1] = w[NV - 1];
 }
 
 // gas + radiation EoS: internal energies of two primitive states (solves in one loop)
@@ -356,7 +360,7 @@ __device__ __forceinline__ void riemann(int solver, const Gas<R>& g, const R* qL
     R wL[NV], wR[NV];
     R TL = R(0), TR = R(0), iL, iR;
     if constexpr (EOS == 1) {
-        to_prim_rad2<NV>(g, qL, qR, wL, wR, iL, iR, TL, TR);
+        to_prim_rad2<NV, DE>(g, qL, qR, wL, wR, iL, iR, TL, TR);
     } else {
         iL = to_prim<R, NV, DE, EOS>(g, qL, wL, &TL);
         iR = to_prim<R, NV, DE, EOS>(g, qR, wR, &TR);

@@ -46,6 +46,7 @@ hipError_t launch_sweep_fp32_hllc_vl(const SweepParams& p, int ndim, int nvar, i
 hipError_t launch_sweep_fp32_mlp(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_sweep_fp64_de(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_sweep_fp64_rad(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
+hipError_t launch_sweep_fp64_de_rad(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_dt_final(const double* partial, int nb, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_dt(const DtParams& p, bool fp32, int nblocks, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_totals(const DtParams& p, bool fp32, int nblocks, double* out, hipStream_t s);

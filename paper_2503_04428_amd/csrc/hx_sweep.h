@@ -152,7 +152,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // limiter and the Riemann solver from the parameters; SPEC = 3 adds the internal-energy monitor
 // (Sect. 2.4: the last field is e, with eq. pressure_fix and the alpha blend; HLLC, limiter from
 // the parameters); SPEC = 4 the gas + radiation EoS (Sect. 2.3, FP64; limiter and Riemann solver
-// from the parameters).
+// from the parameters); SPEC = 5 both (the monitor's P through the EoS; HLLC).
 template <typename R, int NV, int NDIM, int GEOM, int SPEC>
 __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, SPEC>::value))
     sweep_kernel(const SweepParams p)
@@ -162,8 +162,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     constexpr int BY = Tile<NDIM>::BY;
     constexpr int NT = BX * BY;
     constexpr bool MLP = SPEC == 2;
-    constexpr bool DE = SPEC == 3;  // internal-energy monitor: the last field is e (FP64, HLLC)
-    constexpr int EOS = SPEC == 4 ? 1 : 0;  // gas + radiation EoS (FP64)
+    constexpr bool DE = SPEC == 3 || SPEC == 5;  // internal-energy monitor: the last field is e (FP64, HLLC)
+    constexpr int EOS = SPEC == 4 || SPEC == 5 ? 1 : 0;  // gas + radiation EoS (FP64)
     constexpr int S = MLP ? 2 : 1;  // half-width of the slope stencil
     constexpr int RX = BX + 2 * S;
     constexpr int RY = NDIM >= 2 ? BY + 2 * S : 1;
@@ -624,14 +624,25 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             du[v] = R(0);
             dlt[0][v] = dlt[1][v] = dlt[2][v] = R(0);
         }
+        // internal-energy monitor: P of e^n for the half step's -P div(u) ((gamma - 1) e, or
+        // through the gas + radiation EoS, solved once per cell)
+        R pen = R(0);
+        if constexpr (DE && EOS == 1)
+            pen = rad_pressure(gas, qcur[0], temp_from_e(gas, qcur[0], qcur[NV - 1]));
+        auto pe_n = [&]() -> R {
+            if constexpr (EOS == 1)
+                return pen;
+            else
+                return gas.gm1 * qcur[NV - 1];
+        };
         // gas + radiation EoS: internal energies of the six reconstructed face states, solved
         // once here and reused by the positivity check and the final face states
         R ef[EOS ? 3 : 1][2];
         auto pred_cons = [&](int d, const R* wm, const R* wp, R* um, R* up) {
             if constexpr (EOS == 1) {
                 rad_energy2(gas, wm, wp, ef[d][0], ef[d][1]);
-                to_cons_e<NV>(wm, ef[d][0], um);
-                to_cons_e<NV>(wp, ef[d][1], up);
+                to_cons_e<NV, DE>(wm, ef[d][0], um);
+                to_cons_e<NV, DE>(wp, ef[d][1], up);
             } else {
                 to_cons<R, NV, DE, EOS>(gas, wm, um);
                 to_cons<R, NV, DE, EOS>(gas, wp, up);
@@ -659,7 +670,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 du[v] += lamx * (fm[v] - fp[v]);
             // internal energy: -(dt/2) P div(u) with the reconstructed face velocities, P of e^n
             if constexpr (DE)
-                du[NV - 1] += lamx * ((gas.gm1 * qcur[NV - 1]) * (wm[1 + 0] - wp[1 + 0]));
+                du[NV - 1] += lamx * (pe_n() * (wm[1 + 0] - wp[1 + 0]));
         }
         if (NDIM >= 2) {
             if constexpr (!MLP)
@@ -678,7 +689,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 du[v] += lamy * (fm[v] - fp[v]);
             // internal energy: -(dt/2) P div(u) with the reconstructed face velocities, P of e^n
             if constexpr (DE)
-                du[NV - 1] += lamy * ((gas.gm1 * qcur[NV - 1]) * (wm[1 + 1] - wp[1 + 1]));
+                du[NV - 1] += lamy * (pe_n() * (wm[1 + 1] - wp[1 + 1]));
         }
         if (NDIM == 3) {
             commit_own(k + S, qz[S], wz[2 * S]);
@@ -702,7 +713,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 du[v] += lamz * (fm[v] - fp[v]);
             // internal energy: -(dt/2) P div(u) with the reconstructed face velocities, P of e^n
             if constexpr (DE)
-                du[NV - 1] += lamz * ((gas.gm1 * qcur[NV - 1]) * (wm[1 + 2] - wp[1 + 2]));
+                du[NV - 1] += lamz * (pe_n() * (wm[1 + 2] - wp[1 + 2]));
         }
         if (p.gravity != HX_GRAV_NONE) {
             // (dt/2) S(U^n) with S = (0, rho g, m.g, 0)
@@ -749,7 +760,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 for (int v = 0; v < NV; v++)
                     ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
                 if constexpr (EOS == 1)
-                    to_cons_e<NV>(ws, ef[d][side], qs);
+                    to_cons_e<NV, DE>(ws, ef[d][side], qs);
                 else
                     to_cons<R, NV, DE, EOS>(gas, ws, qs);
 #pragma unroll
@@ -797,7 +808,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         // conserved state of face-state primitives ws of axis d, side
         auto face_cons = [&](int d, int side, bool fb, const R* ws, R* out) {
             if constexpr (EOS == 1)
-                to_cons_e<NV>(ws, fb ? e0 : ef[d][side], out);
+                to_cons_e<NV, DE>(ws, fb ? e0 : ef[d][side], out);
             else
                 to_cons<R, NV, DE, EOS>(gas, ws, out);
         };
@@ -845,7 +856,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             for (int v = 0; v < NV; v++)
                 u[v] = bad ? qcur[v] : qcur[v] + du[v];
             if constexpr (DE) {
-                pek = gas.gm1 * u[NV - 1];
+                if constexpr (EOS == 1)
+                    pek = rad_pressure(gas, u[0], temp_from_e(gas, u[0], u[NV - 1]));
+                else
+                    pek = gas.gm1 * u[NV - 1];
                 enk = qcur[NV - 1];
                 alphak = de_alpha<R>(enk, kinetic_energy<R>(qcur), N::from_d(p.de_eps));
             }

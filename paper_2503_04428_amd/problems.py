@@ -627,3 +627,67 @@ def ni_blob3d(n=(24, 20, 16), seed: int = 61, eos: str = "gas") -> Problem:
     U[5] = U[0] * f
     pr = with_ni_heating(base.with_(U0=U, name="ni_blob"))
     return with_gas_rad(pr) if eos == "gas_rad" else pr
+
+
+def hybrid_linlog_faces(r0: float, rb: float, r1: float, n_lin: int, n_log: int) -> np.ndarray:
+    """Hybrid linear-log radial faces (the grid of the paper's 3D SN runs, Sect. 5): n_lin uniform
+    cells on [r0, rb], then n_log cells on [rb, r1] whose widths grow by a constant factor q
+    chosen so that the first of them is as wide as a uniform cell (the spacing is continuous)."""
+    dr = (rb - r0) / n_lin
+    lin = r0 + dr * np.arange(n_lin + 1, dtype=np.float64)
+    span = r1 - rb
+    if not span > n_log * dr:
+        raise ValueError("the log part must widen: need r1 - rb > n_log * (rb - r0) / n_lin")
+    lo, hi = 1.0, 2.0
+    while dr * (hi ** n_log - 1.0) / (hi - 1.0) < span:
+        hi *= 2.0
+    for _ in range(200):  # bisection for q: dr (q^n - 1) / (q - 1) = span
+        q = 0.5 * (lo + hi)
+        if dr * (q ** n_log - 1.0) / (q - 1.0) < span:
+            lo = q
+        else:
+            hi = q
+    q = 0.5 * (lo + hi)
+    k = np.arange(1, n_log + 1, dtype=np.float64)
+    log = rb + dr * (q ** k - 1.0) / (q - 1.0)
+    log[-1] = r1
+    return np.concatenate([lin, log])
+
+
+def sn_wedge3d(n_lin: int = 64, n_log: int = 64, nth: int = 32, nph: int = 32, seed: int = 5,
+               ndim: int = 3, ng: int = GHOSTS_DEFAULT) -> Problem:
+    """Stand-in for the paper's 3D SN ejecta runs (Sect. 5 setup: gas + radiation EoS, 56Ni decay
+    heating, point-mass gravity, internal-energy monitor, minmod, HLLC, reflective inner and
+    transmissive outer radius, hybrid linear-log radial grid), in code units.
+
+    r in [0.1, 10], linear to r = 1 then logarithmic; theta in [pi/4, 3pi/4], phi in [0, pi/2]
+    (periodic). A homologously expanding shocked core (r < 0.5: u_r = 2 r, rho 3 r^-1.5, P 2)
+    inside a static envelope (rho = r^-2.5 with a seeded 5 % lognormal perturbation, P = 1e-3
+    rho^(5/3)); scalar 0 carries 56Ni (f = 0.2 for r < 0.25), scalar 1 the envelope (r > 0.5).
+    Gas + radiation EoS with R = 1, a = 10 (temperatures from the pressures above), G Mc = 0.5,
+    56Ni lifetimes 0.5 and 6.3 time units (the physical ratio), Q = (0.175, 0.373)."""
+    gamma = 5.0 / 3.0
+    fr = hybrid_linlog_faces(0.1, 1.0, 10.0, n_lin, n_log)
+    nr = n_lin + n_log
+    th = (math.pi / 4.0, 3.0 * math.pi / 4.0)
+    fth = uniform_faces(th[0], th[1], nth) if ndim >= 2 else _inactive("sph", 1)
+    fph = uniform_faces(0.0, math.pi / 2.0, nph) if ndim >= 3 else _inactive("sph", 2)
+    n = (nr, nth if ndim >= 2 else 1, nph if ndim >= 3 else 1)
+    rc = 0.5 * (fr[:-1] + fr[1:])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (n[2], n[1], n[0])
+    R = np.broadcast_to(rc[None, None, :], shape)
+    core = R < 0.5
+    rho = np.where(core, 3.0 * R ** -1.5, R ** -2.5) * np.exp(0.05 * rng.standard_normal(size=shape))
+    P = np.where(core, 2.0, 1e-3 * rho ** gamma)
+    ur = np.where(core, 2.0 * R, 0.0)
+    z = np.zeros(shape)
+    fni = np.where(R < 0.25, 0.2, 0.0)
+    fenv = (R > 0.5).astype(np.float64)
+    U = _pack(rho, ur, z, z, P, [fni, fenv], gamma)
+    bc = [["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2]
+    pr = _mk("sn_wedge", ndim, "sph", n, [fr, fth, fph], ng, bc, U, nscalar=2, gamma=gamma, cfl=0.5,
+             riemann="hllc", limiter="minmod", gravity="point", G=1.0, Mc=0.5)
+    pr = with_gas_rad(pr, R=1.0, arad=10.0)
+    pr = with_ni_heating(pr, scalar=0, Q=(0.175, 0.373), tau=(0.5, 6.3), m=1.0)
+    return with_internal_energy(pr, eps=1e-6).with_(name="sn_wedge")

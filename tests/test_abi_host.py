@@ -43,7 +43,7 @@ def test_workspace_bytes_for_the_workloads():
 
 
 @pytest.mark.parametrize("bad", ["ndim", "nghost", "faces", "periodic", "gravity", "r0", "nscalar", "mlp",
-                                 "eos_kind", "eos_fp32", "eos_dual_energy", "eos_R", "eos_mlp"])
+                                 "eos_kind", "eos_fp32", "eos_R", "eos_mlp", "ni_fp32", "ni_scalar", "ni_tau"])
 def test_invalid_configurations_are_rejected(bad):
     pr = P.random_periodic(n=(6, 5, 4), ndim=3, nscalar=1)
     if bad == "ndim":
@@ -71,8 +71,12 @@ def test_invalid_configurations_are_rejected(bad):
         pr = P.with_gas_rad(pr)
     elif bad == "eos_fp32":
         pr = P.with_gas_rad(pr).with_(precision="fp32")
-    elif bad == "eos_dual_energy":
-        pr = P.with_internal_energy(P.with_gas_rad(pr))
+    elif bad == "ni_fp32":
+        pr = P.with_ni_heating(pr).with_(precision="fp32")
+    elif bad == "ni_scalar":
+        pr = P.with_ni_heating(pr, scalar=1)
+    elif bad == "ni_tau":
+        pr = P.with_ni_heating(pr, tau=(0.5, 0.5))
     elif bad == "eos_R":
         pr = P.with_gas_rad(pr).with_(eos_R=0.0)
     elif bad == "eos_mlp":

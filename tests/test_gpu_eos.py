@@ -24,6 +24,19 @@ def H():
     return hydro
 
 
+def _boost(pr, v, seed):
+    """Add a velocity v * w^3, w uniform in [0, 1] per cell, with its kinetic energy (so that the
+    monitor's alpha takes all of its branches)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U = pr.U0.copy()
+    w = rng.uniform(0.0, 1.0, size=U.shape[1:]) ** 3
+    for d in range(3):
+        vd = v[d] * w
+        U[4] += U[1 + d] * vd + 0.5 * U[0] * vd * vd
+        U[1 + d] += U[0] * vd
+    return pr.with_(U0=U)
+
+
 def _pr_over_pg(pr):
     """P_r / P_g per cell of a gas + radiation problem's initial state (oracle EoS)."""
     o = O.Oracle(pr)
@@ -63,6 +76,17 @@ CASES = {
         nr=20, nth=18, ndim=2, nscalar=1, gravity="point",
         bc=[["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2])), 30, None),
     "sedov_sph1d": (lambda: P.with_gas_rad(P.sedov_sph1d(n=200)), 40, None),
+    # with the internal-energy monitor (variant 5: the monitor's P through the EoS)
+    "monitor_wave1d_alpha0": (lambda: P.with_internal_energy(
+        P.with_gas_rad(P.acoustic_wave1d(n=200, amp=1e-2), arad=3.0), eps=1e30), 60, None),
+    "monitor_rand3d_s1_kz5": (lambda: P.with_internal_energy(P.with_gas_rad(_boost(P.random_periodic(
+        n=(31, 23, 19), ndim=3, nscalar=1, seed=56), (6.0, 3.0, -4.0), 56)), eps=2.0), 25, 5),
+    "monitor_boosted_sedov24": (lambda: P.with_internal_energy(P.with_gas_rad(
+        P.boosted_sedov3d(n=24).with_(dual_energy=False, U0=P.boosted_sedov3d(n=24).U0[:-1])), eps=1e-3), 25, None),
+    "monitor_wedge3d_point_minmod": (lambda: P.with_internal_energy(P.with_gas_rad(_boost(P.random_wedge(
+        nr=16, nth=9, nph=12, nscalar=2, gravity="point", limiter="minmod",
+        bc=[["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2]), (0.0, 0.0, 6.0), 57)),
+        eps=2.0), 20, 5),
 }
 
 
@@ -70,7 +94,7 @@ CASES = {
 def test_gas_rad_parity(H, name):
     make, nsteps, kz = CASES[name]
     pr = make()
-    assert pr.eos == "gas_rad"
+    assert pr.eos == "gas_rad" and pr.nvar == pr.U0.shape[0]
     announce(f"gas+rad EoS parity {name} ({nsteps} steps, kz {kz})")
     o = O.Oracle(pr)
     s = H.Solver(pr, zchunk=kz)

@@ -46,6 +46,11 @@ CASES = {
         bc=[["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2])), 0.01, 20, None),
     "wedge2d_late_clock": (lambda: P.with_ni_heating(P.random_wedge(
         nr=20, nth=18, ndim=2, nscalar=1), Q=(2.0, 5.0), tau=(0.3, 1.1), m=0.5), 1e-3, 30, None),
+    # the paper's SN configuration: gas + radiation EoS, monitor, heating, point mass, minmod, HLLC,
+    # hybrid linear-log radial grid
+    "sn_wedge3d_kz6": (lambda: P.sn_wedge3d(n_lin=24, n_log=24, nth=12, nph=12), 0.0, 20, 6),
+    "sn_wedge2d": (lambda: P.sn_wedge3d(n_lin=40, n_log=40, nth=24, ndim=2), 0.2, 30, None),
+    "sn_wedge1d": (lambda: P.sn_wedge3d(n_lin=100, n_log=100, ndim=1), 0.0, 60, None),
 }
 
 
