@@ -89,6 +89,11 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
 /* CFL time step: dt = cfl / max over interior cells of sum_d (|u_d| + c_s)/dx_d. */
 int or_compute_dt(const or_config *c, const double *U, double *dt);
 
+/* Grid shift along axis 0 (Sect. 3.1.1, moving grid): the state U on the faces of c, carried
+ * conservatively onto the faces moved by delta (|delta| <= the narrowest cell incl. the two ghost
+ * layers; spherical: the inner radius stays >= 0), written to Unew.  OR_EINVAL otherwise. */
+int or_shift_grid(const or_config *c, const double *U, double delta, double *Unew);
+
 /* Conserved totals sum_cells U_v dV, one per variable. */
 void or_totals(const or_config *c, const double *U, double *tot);
 

@@ -67,6 +67,8 @@ def lib(path: str = LIB_PATH):
         L.or_eos_state.restype = C.c_double
         L.or_eos_energy.argtypes = [C.POINTER(OrConfig), C.c_double, C.c_double]
         L.or_eos_energy.restype = C.c_double
+        L.or_shift_grid.argtypes = [C.POINTER(OrConfig), _DP, C.c_double, _DP]
+        L.or_shift_grid.restype = C.c_int
         L.or_ni_rate.argtypes = [C.POINTER(OrConfig), C.c_double]
         L.or_ni_rate.restype = C.c_double
         L.or_de_alpha.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -243,6 +245,18 @@ class Oracle:
         P, cs = C.c_double(), C.c_double()
         T = self._L.or_eos_state(self._cfgp(), float(rho), float(e), C.byref(P), C.byref(cs))
         return T, P.value, cs.value
+
+    def shift_grid(self, U: np.ndarray, delta: float) -> np.ndarray:
+        """Move every face of axis 0 by delta and carry U over conservatively (Sect. 3.1.1, moving
+        grid); the oracle's own faces move with it."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
+        out = np.empty_like(U)
+        st = self._L.or_shift_grid(self._cfgp(), _ptr(U), float(delta), _ptr(out))
+        if st == EINVAL:
+            raise ValueError("oracle: invalid grid shift")
+        self._faces[0] = self._faces[0] + float(delta)
+        self.cfg.faces[0] = _ptr(self._faces[0])
+        return out
 
     def ni_rate(self, t: float) -> float:
         """56Ni decay heating per unit mass of 56Ni at time t (eq. heating_ni)."""
