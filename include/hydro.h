@@ -158,6 +158,16 @@ hx_status hx_set_zchunk(hx_ctx *ctx, int kz);
  * 3D step).  HX_EINVAL for null arguments. */
 hx_status hx_get_zchunk(hx_ctx *ctx, int *kz);
 
+/* Moving grid (Sect. 3.1.1): move every face of axis 0 (r in spherical geometry) by delta and
+ * carry the current state over conservatively: minmod-limited linear profiles of the conserved
+ * variables about each cell's volume centroid, integrated over the overlaps with the new cells
+ * (measure dx, or r^2 dr in spherical geometry), the boundary images supplying what enters; a
+ * cell whose result would not be physical takes the piecewise-constant remap.  |delta| must not
+ * exceed the narrowest cell of axis 0 (ghost layers included) and a spherical inner radius must
+ * stay >= 0.  Between steps; synchronises the stream (the geometry tables are rebuilt and
+ * uploaded).  HX_EINVAL for an invalid delta, HX_ESTATE before hx_set_state. */
+hx_status hx_shift_grid(hx_ctx *ctx, double delta);
+
 /* The decay clock of the 56Ni heating: with ni_heating on, every step advances it by its dt on the
  * device (also with hx_step_device); without, steps leave it alone.  hx_create starts it at 0.
  * hx_set_time sets it (asynchronous); hx_get_time synchronises and reads it.  HX_EINVAL for null

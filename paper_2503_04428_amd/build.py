@@ -8,6 +8,7 @@ Each HIP translation unit is compiled separately (no relocatable device code):
    internal-energy monitor, hx_sweep_fp64_rad.hip the FP64 sweep with the gas + radiation EoS,
    hx_sweep_fp64_de_rad.hip both)
   hx_reduce.hip      dt / totals / enclosed-mass reductions, -ffp-contract=off
+  hx_shift.hip       grid shift along axis 0 (conservative remap), -ffp-contract=off
   hx_mlp.hip         learned limiter: BF16-MFMA evaluation, training samples, FP32 training
   hx_abi.hip         C ABI host code
 Packed FP32 instructions are disabled for all device code.
@@ -40,6 +41,7 @@ UNITS = {
     "hx_sweep_fp32_hllc_vl.hip": [],
     "hx_sweep_fp32_mlp.hip": [],
     "hx_reduce.hip": ["-ffp-contract=off"],
+    "hx_shift.hip": ["-ffp-contract=off"],
     "hx_mlp.hip": ["-ffp-contract=off"],
     "hx_abi.hip": ["-ffp-contract=off"],
 }

@@ -72,7 +72,7 @@ struct Layout {
     size_t state[2];
     size_t tab[3][3];  // cm, cp, w per axis
     size_t rabs, sabs, rf, vr, hr, ct, sf;
-    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp, time;
+    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp, time, xfaces;
     size_t total;
     int ntab[3];
     int nchunk, nred;
@@ -233,6 +233,7 @@ Layout layout(const hx_config* c)
     L.tot = take(sizeof(double) * nv);
     L.mlp = take(sizeof(float) * HX_MLP_NPARAM);
     L.time = take(sizeof(double));  // the decay clock of the 56Ni heating
+    L.xfaces = take(sizeof(double) * (c->n[0] + 1 + 2 * c->nghost));  // axis-0 faces (grid shift)
     L.total = off;
     return L;
 }
@@ -363,6 +364,7 @@ void build_geometry(hx_ctx* x, std::vector<double>& h, std::vector<std::pair<siz
         }
     }
     push(x->L.gr, gr);
+    push(x->L.xfaces, x->faces[0]);
 }
 
 hx::Geo geo_of(hx_ctx* x)
@@ -577,6 +579,57 @@ hx_status hx_create(const hx_config* cfg, void* d_workspace, size_t workspace_by
         return fail(HX_EHIP, "create: %s", hipGetErrorString(e));
     }
     *out = x;
+    return HX_OK;
+}
+
+hx_status hx_shift_grid(hx_ctx* x, double delta)
+{
+    if (!x)
+        return fail(HX_EINVAL, "null context");
+    if (!x->have_state)
+        return fail(HX_ESTATE, "grid shift before set_state");
+    const hx_config& c = x->cfg;
+    const int ng = c.nghost, n0 = c.n[0];
+    std::vector<double>& f = x->faces[0];
+    if (!std::isfinite(delta))
+        return fail(HX_EINVAL, "non-finite shift");
+    for (int i = ng - 2; i < n0 + ng + 2; i++)
+        if (!(std::fabs(delta) <= f[i + 1] - f[i]))
+            return fail(HX_EINVAL, "shift %g wider than cell %d of axis 0 (%g)", delta, i - ng, f[i + 1] - f[i]);
+    if (c.geom == HX_GEOM_SPH) {
+        const double r0 = f[ng] + delta;
+        if (r0 < 0.0 || (r0 == 0.0 && c.bc[0][0] != HX_BOUNDARY_REFLECTIVE))
+            return fail(HX_EINVAL, "the shift would move the inner radius to %g", r0);
+    }
+    hx::ShiftParams p;
+    p.U = x->state[x->cur];
+    p.Unew = x->state[1 - x->cur];
+    p.n0 = n0;
+    p.ng = ng;
+    p.plane = x->ncells;
+    p.nvar = x->nvar;
+    p.sph = c.geom == HX_GEOM_SPH;
+    p.de = c.dual_energy ? 1 : 0;
+    p.bc0[0] = c.bc[0][0];
+    p.bc0[1] = c.bc[0][1];
+    p.xf = at<double>(x, x->L.xfaces);
+    p.delta = delta;
+    HIPCHECK(hx::launch_shift(p, x->fp32, x->stream));
+    x->cur = 1 - x->cur;
+    x->dtpart_valid = false;
+    // the staging of the last geometry upload is reused: wait for the queued work first
+    HIPCHECK(hipStreamSynchronize(x->stream));
+    for (double& v : f)
+        v += delta;
+    x->host_tabs.clear();
+    std::vector<std::pair<size_t, size_t>> spans;
+    build_geometry(x, x->host_tabs, spans);
+    for (size_t s = 0; s < spans.size(); s++) {
+        const size_t beg = spans[s].second;
+        const size_t end = s + 1 < spans.size() ? spans[s + 1].second : x->host_tabs.size();
+        HIPCHECK(hipMemcpyAsync(x->ws + spans[s].first, x->host_tabs.data() + beg, sizeof(double) * (end - beg),
+                                hipMemcpyHostToDevice, x->stream));
+    }
     return HX_OK;
 }
 

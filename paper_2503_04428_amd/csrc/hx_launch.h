@@ -24,6 +24,21 @@ struct DtParams {
     int* flag;
 };
 
+struct ShiftParams {
+    const void* U;       // state on the old faces
+    void* Unew;          // state on the faces moved by delta
+    int n0, ng;
+    long long plane;     // cells per field
+    int nvar;
+    int sph;             // 1: measure r^2 dr (spherical), 0: dx
+    int de;              // 1: the last field is the monitored internal energy
+    int bc0[2];          // boundary kinds of axis 0
+    const double* xf;    // the n0 + 1 + 2 ng old faces of axis 0, ghost faces included
+    double delta;
+};
+
+hipError_t launch_shift(const ShiftParams& p, bool fp32, hipStream_t s);
+
 struct ShellParams {
     const void* U;       // density field (first variable of the state)
     int n[3];

@@ -57,7 +57,7 @@ _lib = None
 # names of the exported entry points, as declared in include/hydro.h
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
            "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
-           "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
+           "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_shift_grid", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
            "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_adam", "hx_last_error", "hx_destroy"]
 
 
@@ -87,6 +87,7 @@ def load_library():
     L.hx_set_zchunk.argtypes = [vp, C.c_int]
     L.hx_get_zchunk.argtypes = [vp, C.POINTER(C.c_int)]
     L.hx_set_time.argtypes = [vp, C.c_double]
+    L.hx_shift_grid.argtypes = [vp, C.c_double]
     L.hx_get_time.argtypes = [vp, C.POINTER(C.c_double)]
     L.hx_enclosed_mass.argtypes = [vp, _DP]
     L.hx_mlp_eval.argtypes = [vp, vp, C.c_longlong, vp, vp]
@@ -279,6 +280,10 @@ class Solver:
         v = C.c_int(0)
         self._call(self.L.hx_get_zchunk(self.ctx, C.byref(v)))
         return v.value
+
+    def shift_grid(self, delta: float):
+        """Move the faces of axis 0 by delta and carry the state over (moving grid)."""
+        self._call(self.L.hx_shift_grid(self.ctx, float(delta)))
 
     def set_time(self, t: float):
         """Set the decay clock of the 56Ni heating (every step advances it by its dt)."""
