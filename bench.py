@@ -81,6 +81,35 @@ def run_form(hydro, torch, prob, form, steps, warmup, zchunk, weights=None):
     return out
 
 
+def run_shift(hydro, torch, prob, nshift):
+    """Grid shifts (moving grid) of the workload's state, alternating +/- half the narrowest radial
+    cell; HIP events around each call (the remap kernel and the geometry upload)."""
+    import numpy as np
+
+    s = hydro.Solver(prob)
+    s.set_state(prob.U0)
+    d = 0.5 * float(np.diff(prob.faces[0]).min())
+    stream = s.stream
+    s.shift_grid(d)
+    s.shift_grid(-d)
+    ms = []
+    for k in range(nshift):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            s.shift_grid(d if k % 2 == 0 else -d)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    s.check()
+    s.close()
+    avg = sum(ms) / len(ms)
+    alg = 2 * prob.nvar * 8 * prob.ncells
+    return {"calls": nshift, "ms_avg": avg, "ms_min": min(ms), "algorithmic_bytes": alg,
+            "GB/s": alg / (avg * 1e-3) / 1e9, "frac_of_hbm": alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "delta": d}
+
+
 def monotone_fraction(torch, U, gamma):
     """Share of (cell, axis, primitive) stencils with differences of one sign on both sides, i.e.
     where the learned limiter evaluates its network (interior cells only)."""
@@ -268,6 +297,11 @@ def main():
             f"(min {r['sweep_ms_min']:.3f}), {cells * args.steps / r['wall_s']:.3e} zone-cycles/s, kz {r['zchunk']}")
         results[form] = r
 
+    shift_out = None
+    if args.workload == "sn":
+        shift_out = run_shift(hydro, torch, prob, 20)
+        log(f"grid shift: {shift_out['ms_avg']:.3f} ms per call, {shift_out['GB/s']:.0f} GB/s algorithmic")
+
     learned_out = None
     if args.learned_steps > 0:
         learned_out = run_learned(hydro, torch, problems, args.learned_steps, args.warmup, args.learned_n,
@@ -356,6 +390,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
     }
+    if shift_out is not None:
+        line["grid_shift"] = shift_out
     print(json.dumps(line), flush=True)
 
 

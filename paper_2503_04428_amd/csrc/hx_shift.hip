@@ -16,7 +16,6 @@ namespace hx {
 namespace {
 
 constexpr int SB = 256;
-constexpr int SMAXV = 10;
 
 __device__ __forceinline__ double m0_of(int sph, double a, double b)
 {
@@ -58,7 +57,7 @@ __device__ __forceinline__ int image0(int i, int n, int lo, int hi, bool& flip)
     return i;
 }
 
-template <typename R>
+template <typename R, int NV>
 __global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p)
 {
     const long long ncell = p.plane;
@@ -67,70 +66,97 @@ __global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p)
         return;
     const R* __restrict__ U = (const R*)p.U;
     R* __restrict__ Un = (R*)p.Unew;
-    const int n = p.n0, nv = p.nvar;
+    const int n = p.n0;
     const int i = (int)(c % n);
-    const long long row = c / n;  // (j, k) row: its cells are row * n + i
+    const long long rowoff = c - i;  // first cell of this (j, k) row
     const double* xf = p.xf + p.ng;  // xf[i]: face i of axis 0, ghost faces at negative indices
     const double a = xf[i] + p.delta, b = xf[i + 1] + p.delta;
     const double vnew = m0_of(p.sph, a, b);
-    const int mfirst = p.delta > 0.0 ? i : i - 1;
-    double lin[SMAXV], con[SMAXV];
+    // the two old cells under the new one are m0 and m0 + 1; their slope stencils span m0 - 1 .. m0 + 2
+    const int m0 = p.delta > 0.0 ? i : i - 1;
+    long long src[4];
+    double sgn[4];  // -1 for the normal momentum of a reflected image
 #pragma unroll
-    for (int v = 0; v < SMAXV; v++)
-        lin[v] = con[v] = 0.0;
-    for (int m = mfirst; m <= mfirst + 1; m++) {
-        const double lo = fmax(a, xf[m]), hi = fmin(b, xf[m + 1]);
-        if (!(hi > lo))
-            continue;
-        double cm[3];
-        int src[3];
-        bool fl[3];
-#pragma unroll
-        for (int s = 0; s < 3; s++) {
-            const double fa = xf[m - 1 + s], fb = xf[m + s];
-            cm[s] = m1_of(p.sph, fa, fb) / m0_of(p.sph, fa, fb);
-            src[s] = image0(m - 1 + s, n, p.bc0[0], p.bc0[1], fl[s]);
-        }
-        const double w0 = m0_of(p.sph, lo, hi), w1 = m1_of(p.sph, lo, hi);
-#pragma unroll
-        for (int v = 0; v < SMAXV; v++) {
-            if (v < nv) {
-                double q[3];
-#pragma unroll
-                for (int s = 0; s < 3; s++) {
-                    q[s] = (double)U[(long long)v * ncell + row * n + src[s]];
-                    if (v == 1 && fl[s])
-                        q[s] = -q[s];
-                }
-                const double sl = minmod_d((q[1] - q[0]) / (cm[1] - cm[0]), (q[2] - q[1]) / (cm[2] - cm[1]));
-                lin[v] += q[1] * w0 + sl * (w1 - cm[1] * w0);
-                con[v] += q[1] * w0;
-            }
-        }
+    for (int s = 0; s < 4; s++) {
+        bool fl;
+        src[s] = rowoff + image0(m0 - 1 + s, n, p.bc0[0], p.bc0[1], fl);
+        sgn[s] = fl ? -1.0 : 1.0;
     }
-    const double m2 = lin[1] * lin[1] + lin[2] * lin[2] + lin[3] * lin[3];
-    double elast = 0.0;
+    double q[4][NV], cm[4];
 #pragma unroll
-    for (int v = 0; v < SMAXV; v++)
-        if (v == nv - 1)
-            elast = lin[v];
-    const bool ok = lin[0] > 0.0 && 2.0 * lin[0] * lin[4] - m2 > 0.0 && (!p.de || elast > 0.0);
+    for (int v = 0; v < NV; v++)
 #pragma unroll
-    for (int v = 0; v < SMAXV; v++)
-        if (v < nv)
-            Un[(long long)v * ncell + c] = (R)((ok ? lin[v] : con[v]) / vnew);
+        for (int s = 0; s < 4; s++)
+            q[s][v] = (double)U[(long long)v * ncell + src[s]];
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+        q[s][1] = sgn[s] * q[s][1];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const double fa = xf[m0 - 1 + s], fb = xf[m0 + s];
+        cm[s] = m1_of(p.sph, fa, fb) / m0_of(p.sph, fa, fb);
+    }
+    // overlaps of the new cell with the old cells m0 and m0 + 1 (an empty one adds zeros: the same
+    // sums as skipping it, since the sums start at +0)
+    double w0[2], w1[2];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const double lo = fmax(a, xf[m0 + j]), hi = fmin(b, xf[m0 + j + 1]);
+        const bool has = hi > lo;
+        w0[j] = has ? m0_of(p.sph, lo, hi) : 0.0;
+        w1[j] = has ? m1_of(p.sph, lo, hi) : 0.0;
+    }
+    // content of field v under the new cell: with the linear profiles, and with constant ones
+    auto content = [&](int v, double& lin, double& con) {
+        lin = 0.0;
+        con = 0.0;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const double sl = minmod_d((q[j + 1][v] - q[j][v]) / (cm[j + 1] - cm[j]),
+                                       (q[j + 2][v] - q[j + 1][v]) / (cm[j + 2] - cm[j + 1]));
+            lin += q[j + 1][v] * w0[j] + sl * (w1[j] - cm[j + 1] * w0[j]);
+            con += q[j + 1][v] * w0[j];
+        }
+    };
+    // physical check on the linear result (rho, E, momenta and the monitored e)
+    double h[5], c5;
+#pragma unroll
+    for (int v = 0; v < 5; v++)
+        content(v, h[v], c5);
+    double el = 1.0;
+    if (p.de)
+        content(NV - 1, el, c5);
+    const double m2 = h[1] * h[1] + h[2] * h[2] + h[3] * h[3];
+    const bool ok = h[0] > 0.0 && 2.0 * h[0] * h[4] - m2 > 0.0 && el > 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        double lin, con;
+        content(v, lin, con);
+        Un[(long long)v * ncell + c] = (R)((ok ? lin : con) / vnew);
+    }
+}
+
+template <typename R>
+hipError_t go_shift(const ShiftParams& p, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((p.plane + SB - 1) / SB);
+    switch (p.nvar) {
+    case 5: shift_kernel<R, 5><<<nb, SB, 0, s>>>(p); break;
+    case 6: shift_kernel<R, 6><<<nb, SB, 0, s>>>(p); break;
+    case 7: shift_kernel<R, 7><<<nb, SB, 0, s>>>(p); break;
+    case 8: shift_kernel<R, 8><<<nb, SB, 0, s>>>(p); break;
+    case 9: shift_kernel<R, 9><<<nb, SB, 0, s>>>(p); break;
+    case 10: shift_kernel<R, 10><<<nb, SB, 0, s>>>(p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_shift(const ShiftParams& p, bool fp32, hipStream_t s)
 {
-    const long long nb = (p.plane + SB - 1) / SB;
-    if (fp32)
-        shift_kernel<float><<<(unsigned)nb, SB, 0, s>>>(p);
-    else
-        shift_kernel<double><<<(unsigned)nb, SB, 0, s>>>(p);
-    return hipGetLastError();
+    return fp32 ? go_shift<float>(p, s) : go_shift<double>(p, s);
 }
 
 }  // namespace hx
