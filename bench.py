@@ -184,10 +184,10 @@ def recorded_traffic(form):
     return None
 
 
-def recorded_flops():
-    """Algorithmic FP64 flops of one Sedov zone-cycle from the committed op-count record (the
-    oracle's own operations, each face flux counted once), or None."""
-    path = os.path.join(ROOT, "profiles", "sweep_sedov256_flops.md")
+def recorded_flops(name="sweep_sedov256_flops.md"):
+    """Algorithmic FP64 flops of one zone-cycle of a workload from its committed op-count record
+    (the oracle's own operations, each face flux counted once), or None."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         for line in open(path):
             if line.startswith("FLOPS_JSON"):
@@ -352,6 +352,10 @@ def main():
     sedov256 = args.n == 256 and args.workload == "sedov"
     traffic_bytes = recorded_traffic(head["form"]) if sedov256 else None
     flops_zc = recorded_flops() if sedov256 else None
+    # the EoS sweeps are bound by ALU issue (Newton steps); their headline view is the ALU one
+    alu_bound = args.workload in ("rad", "sn")
+    if alu_bound:
+        flops_zc = recorded_flops({"rad": "sweep_sedov_gas_rad_flops.md", "sn": "sweep_sn_wedge_flops.md"}[args.workload])
     alu = None
     if flops_zc is not None:
         peak = FP64_VECTOR_PEAK_TFLOPS if head["form"] == "fp64" else FP32_VECTOR_PEAK_TFLOPS
@@ -390,6 +394,13 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
     }
+    if alu_bound and alu is not None:
+        hbm = dict(line["roofline"])
+        hbm.pop("alu")
+        line["roofline"] = {"bound": "alu", "achieved": alu["achieved"], "peak": alu["peak"], "unit": "TFLOP/s",
+                            "frac": alu["frac"], "traffic": None, "kernel": hbm["kernel"],
+                            "flops_per_zone_cycle": alu["flops_per_zone_cycle"],
+                            "algorithmic_flops_per_launch": alu["algorithmic_flops_per_launch"], "hbm": hbm}
     if shift_out is not None:
         line["grid_shift"] = shift_out
     print(json.dumps(line), flush=True)

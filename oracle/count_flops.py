@@ -6,6 +6,8 @@ profiles/, which the benchmark reads as the algorithmic flops of one zone-cycle 
 and sqrt count one flop each).
 
     python -m oracle.count_flops [--n 256] [--out profiles/sweep_sedov256_flops.md]
+    python -m oracle.count_flops --workload rad --n 64 --out profiles/sweep_sedov_gas_rad_flops.md
+    python -m oracle.count_flops --workload sn --n 64 --out profiles/sweep_sn_wedge_flops.md
 """
 from __future__ import annotations
 
@@ -40,17 +42,29 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "sweep_sedov256_flops.md"))
+    ap.add_argument("--workload", default="sedov", choices=["sedov", "rad", "sn"])
     a = ap.parse_args()
-    rec = count(P.sedov3d(n=a.n))
+    if a.workload == "sedov":
+        prob = P.sedov3d(n=a.n)
+        title = f"Sedov {a.n}^3 (7 fields, HLLC, van Leer)"
+    elif a.workload == "rad":
+        prob = P.with_gas_rad(P.sedov3d(n=a.n))
+        title = f"Sedov {a.n}^3 with the gas + radiation EoS (7 fields, HLLC, van Leer; R 1, a 30)"
+    else:
+        prob = P.sn_wedge3d(n_lin=a.n, n_log=a.n, nth=a.n // 4, nph=a.n // 4)
+        title = (f"SN wedge {2 * a.n}x{a.n // 4}x{a.n // 4} (gas + radiation EoS, internal-energy monitor, "
+                 f"56Ni heating, point mass, minmod, HLLC; 8 fields)")
+    rec = count(prob)
     pz = rec["per_zone_cycle"]
     lines = [
-        f"# Algorithmic FP64 work per zone-cycle: Sedov {a.n}^3 (7 fields, HLLC, van Leer)",
+        f"# Algorithmic FP64 work per zone-cycle: {title}",
         "",
         "Counted by the op-counting build of the oracle (oracle/opcount.cpp, the oracle's C source",
         "with a counting FP64 type) over the first step of the workload; one flop each for add/sub,",
         "mul, div and sqrt.  Command (repository root):",
         "",
-        f"    python -m oracle.count_flops --n {a.n}",
+        f"    python -m oracle.count_flops --workload {a.workload} --n {a.n}"
+        + ("" if a.workload == "sedov" else f" --out {os.path.relpath(a.out, ROOT)}"),
         "",
         "| add/sub | mul | div | sqrt | flops | comparisons | min/max/abs |",
         "|---|---|---|---|---|---|---|",
