@@ -214,9 +214,10 @@ class Oracle:
         return out
 
     def run(self, U: np.ndarray, nsteps: int | None = None, t_end: float | None = None,
-            dt_fixed: float | None = None):
-        """Advance with the CFL time step (or a fixed one); returns (U, t, steps, dts)."""
-        t = 0.0
+            dt_fixed: float | None = None, t0: float = 0.0):
+        """Advance from time t0 with the CFL time step (or a fixed one), the last step clipped to
+        t_end; returns (U, t, steps, dts)."""
+        t = t0
         steps = 0
         dts = []
         while True:
@@ -232,7 +233,7 @@ class Oracle:
                     raise FloatingPointError("oracle: nonphysical state at dt")
             if t_end is not None:
                 dt = min(dt, t_end - t)
-            U, st = self.step(U, dt)
+            U, st = self.step(U, dt, t)
             if st:
                 raise FloatingPointError(f"oracle: nonphysical state after step {steps}")
             t += dt

@@ -259,6 +259,23 @@ class Solver:
             self.compute_dt_device()
             self.step_device()
 
+    def run(self, t_end: float | None = None, nsteps: int | None = None, t0: float = 0.0):
+        """Advance from time t0 with the CFL time step, the last step clipped to t_end (host time
+        step: one synchronisation per step); returns (t, steps).  The decay clock of the 56Ni
+        heating is set to t0 first."""
+        if t_end is None and nsteps is None:
+            raise ValueError("run needs t_end or nsteps")
+        self.set_time(t0)
+        t, steps = t0, 0
+        while (nsteps is None or steps < nsteps) and (t_end is None or t < t_end * (1 - 1e-14)):
+            dt = self.compute_dt()
+            if t_end is not None:
+                dt = min(dt, t_end - t)
+            self.step(dt)
+            t += dt
+            steps += 1
+        return t, steps
+
     def totals(self) -> np.ndarray:
         out = np.zeros(self.nvar)
         self._call(self.L.hx_totals(self.ctx, out.ctypes.data_as(_DP)))

@@ -364,3 +364,18 @@ def test_fp64_parity_beyond_32bit_offsets(H):
     del G
     s.close()
     torch.cuda.empty_cache()
+
+
+def test_run_to_t_end(H):
+    """Sod to t = 0.2 with the last step clipped: the same step sequence and final time as the
+    oracle's run, the state to the FP64 bar."""
+    prob = P.sod(n=400)
+    announce("run to t_end (Sod 400)")
+    Uo, to, no, _ = O.Oracle(prob).run(prob.U0.copy(), t_end=0.2)
+    s = H.Solver(prob)
+    s.set_state(prob.U0)
+    t, n = s.run(t_end=0.2)
+    G = s.state_numpy()
+    s.close()
+    assert n == no and t == to and abs(t - 0.2) < 1e-15
+    assert_parity(G, Uo, what="sod run to t_end")
