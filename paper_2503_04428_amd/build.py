@@ -6,7 +6,8 @@ Each HIP translation unit is compiled separately (no relocatable device code):
   (the *_hllc_vl units fix HLLC + van Leer at compile time; the others take them at run time;
    hx_sweep_fp32_mlp.hip is the learned-limiter form, hx_sweep_fp64_de.hip the FP64 sweep with the
    internal-energy monitor, hx_sweep_fp64_rad.hip the FP64 sweep with the gas + radiation EoS,
-   hx_sweep_fp64_de_rad.hip both)
+   hx_sweep_fp64_de_rad.hip both; hx_sweep_fp64_3d_ilp.hip the 3D one-wave-per-SIMD FP64 sweeps
+   built with the ILP machine scheduler)
   hx_reduce.hip      dt / totals / enclosed-mass reductions, -ffp-contract=off
   hx_shift.hip       grid shift along axis 0 (conservative remap), -ffp-contract=off
   hx_mlp.hip         learned limiter: BF16-MFMA evaluation, training samples, FP32 training
@@ -31,12 +32,14 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
+SCHED_ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
 UNITS = {
     "hx_sweep_fp64.hip": ["-ffp-contract=off"],
     "hx_sweep_fp64_hllc_vl.hip": ["-ffp-contract=off"],
     "hx_sweep_fp64_de.hip": ["-ffp-contract=off"],
     "hx_sweep_fp64_rad.hip": ["-ffp-contract=off"],
     "hx_sweep_fp64_de_rad.hip": ["-ffp-contract=off"],
+    "hx_sweep_fp64_3d_ilp.hip": ["-ffp-contract=off", "-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "hx_sweep_fp32.hip": [],
     "hx_sweep_fp32_hllc_vl.hip": [],
     "hx_sweep_fp32_mlp.hip": [],
@@ -53,6 +56,13 @@ def _compile(src: str, extra: list) -> str:
     tune = os.environ.get("HX_EXTRA_FLAGS", "").split()
     cmd = [HIPCC, *COMMON, *extra, *tune, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and SCHED_ILP[1] in cmd:
+        # the ILP scheduler is an optional code-generation choice: without it the unit computes the
+        # same results, so a compiler that cannot build it with that scheduler builds it without
+        k = cmd.index(SCHED_ILP[1])
+        cmd = cmd[:k - 1] + cmd[k + 1:]
+        print(f"note: {src} built without {SCHED_ILP[1]} (the compiler failed with it)", file=sys.stderr)
+        r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
     return obj

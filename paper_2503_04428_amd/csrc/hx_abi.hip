@@ -470,12 +470,15 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
             return c.eos == HX_EOS_GAS_RAD ? hx::launch_sweep_fp64_de_rad(p, c.ndim, x->nvar, c.geom, x->stream, occ)
                                            : hx::launch_sweep_fp64_de(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (c.eos == HX_EOS_GAS_RAD)
-            return hx::launch_sweep_fp64_rad(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+            return c.ndim == 3 ? hx::launch_sweep_fp64_3d_ilp(p, 4, x->nvar, c.geom, x->stream, occ)
+                               : hx::launch_sweep_fp64_rad(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (c.limiter == HX_LIMITER_MLP)
             return hx::launch_sweep_fp32_mlp(p, c.ndim, x->nvar, c.geom, x->stream, occ);
         if (x->fp32)
             return spec ? hx::launch_sweep_fp32_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream, occ)
                         : hx::launch_sweep_fp32_generic(p, c.ndim, x->nvar, c.geom, x->stream, occ);
+        if (spec && c.ndim == 3 && x->nvar >= 7)
+            return hx::launch_sweep_fp64_3d_ilp(p, 1, x->nvar, c.geom, x->stream, occ);
         return spec ? hx::launch_sweep_fp64_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream, occ)
                     : hx::launch_sweep_fp64_generic(p, c.ndim, x->nvar, c.geom, x->stream, occ);
     };

@@ -153,7 +153,9 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // (Sect. 2.4: the last field is e, with eq. pressure_fix and the alpha blend; HLLC, limiter from
 // the parameters); SPEC = 4 the gas + radiation EoS (Sect. 2.3, FP64; limiter and Riemann solver
 // from the parameters); SPEC = 5 both (the monitor's P through the EoS; HLLC).
-template <typename R, int NV, int NDIM, int GEOM, int SPEC>
+// TAG only separates otherwise identical instantiations built in different units (with different
+// code-generation options), so that each unit launches its own.
+template <typename R, int NV, int NDIM, int GEOM, int SPEC, int TAG = 0>
 __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, SPEC>::value))
     sweep_kernel(const SweepParams p)
 {

@@ -7,7 +7,7 @@ namespace hx {
 
 // Launches the instantiation that matches the run-time shape, or, with occ != nullptr, only
 // reports how many of its workgroups fit on one compute unit.
-template <typename R, int NV, int NDIM, int SPEC>
+template <typename R, int NV, int NDIM, int SPEC, int TAG = 0>
 static hipError_t go(const SweepParams& p, int geom, hipStream_t s, int* occ)
 {
     const dim3 grid = sweep_grid(NDIM, p.n, p.kz), block = sweep_block(NDIM);
@@ -18,8 +18,8 @@ static hipError_t go(const SweepParams& p, int geom, hipStream_t s, int* occ)
         return hipGetLastError();
     };
     if (geom == HX_SPH)
-        return run(sweep_kernel<R, NV, NDIM, HX_SPH, SPEC>);
-    return run(sweep_kernel<R, NV, NDIM, HX_CART, SPEC>);
+        return run(sweep_kernel<R, NV, NDIM, HX_SPH, SPEC, TAG>);
+    return run(sweep_kernel<R, NV, NDIM, HX_CART, SPEC, TAG>);
 }
 
 template <typename R, int NV, int SPEC>
