@@ -235,6 +235,10 @@ class Solver:
         self.stream.synchronize()
         return t.cpu().numpy()
 
+    def state(self) -> np.ndarray:
+        """The current conserved state as a host FP64 array [nvar][n3][n2][n1]."""
+        return self.state_numpy()
+
     # ----------------------------------------------------------------- stepping
     def compute_dt(self) -> float:
         dt = C.c_double(0.0)
