@@ -576,13 +576,13 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 
         // -------------------------------------------------------------- predictor, plane k
         bool fzk = false;
-        int kk = 0, gz = 0;
+        int gz = 0;
         double w2k = 0.0;  // z width of plane k
         R cmz = R(0), cpz = R(0), lamz = R(0);
         double g[3] = {gcol[0], gcol[1], gcol[2]};
         if (NDIM == 3) {
             const int kc = clamp_ghost(k, n2, ng);
-            kk = bc_image(kc, n2, ng, p.bc[2][0], p.bc[2][1], fzk);
+            bc_image(kc, n2, ng, p.bc[2][0], p.bc[2][1], fzk);  // sets the z-mirror flag
             gz = kc + ng;
             cmz = N::from_d(p.geo.cm[2][gz]);
             cpz = N::from_d(p.geo.cp[2][gz]);
@@ -996,7 +996,6 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 if constexpr (DE)
                     acc[NV - 1] += mu * (pek * (ufx - ufxr));
             } else {
-                const int kin = NDIM == 3 ? k : 0;
                 dph = NDIM == 3 ? w2k : p.geo.w[2][0];
                 const double ctj = p.geo.ct[jj];
                 dV = p.geo.vr[ii] * ctj * dph;

@@ -1,8 +1,12 @@
 """GPU parity of the gas + radiation EoS (Sect. 2.3; variant 4 of the fused sweep, FP64) against the
 FP64 oracle on the same seeded inputs: 1D-3D, Cartesian and spherical, both Riemann solvers, every
 limiter but the learned one, every boundary kind, gravity, ragged z chunks, radiation- and
-gas-dominated states in one grid.  FP64 bar as for the other sweeps: per cell
-|dU| <= 1e-12 |U_oracle| + 1e-14 max|U_oracle,field|; the time step to 1e-14."""
+gas-dominated states in one grid.  FP64 bar: per cell |dU| <= 1e-12 |U_oracle| + 1e-14 s_field,
+s_field = max|U_oracle,field|, with the three momenta on one flow scale, at least
+sqrt(max rho max E); the time step to 1e-14.  The kernel finds the temperature with a refined
+hardware reciprocal and the oracle with IEEE division, so the two agree to a few ulps of T, not
+bit for bit; in near-static and linear-wave flows a momentum is a small difference of pressure
+terms, and those ulps of P are large against the momentum itself but not against the flow scale."""
 import numpy as np
 import pytest
 
@@ -112,7 +116,7 @@ def test_gas_rad_parity(H, name):
     s.check()
     s.close()
     print(f"{name}: max relative difference {max_rel(G, U):.3e}")
-    assert_parity(G, U, what=name)
+    assert_parity(G, U, what=name, flow_scale=True)
 
 
 def test_cases_span_both_regimes():
@@ -152,7 +156,7 @@ def test_gas_rad_full_size_sedov_sampled(H):
     for lo, hi in boxes:
         ob, st = o.step_box(U0, dt, lo, hi)
         gb = Ug[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
-        assert_parity(gb, ob, what=f"gas+rad sedov256 box {lo}-{hi}")
+        assert_parity(gb, ob, what=f"gas+rad sedov256 box {lo}-{hi}", flow_scale=True)
 
 
 def test_gas_rad_nonphysical_state_reported(H):
