@@ -35,16 +35,19 @@ template <typename R>
 struct Gas {
     R gm1, inv_gm1, gamma;
     R Rg, arad;  // gas + radiation EoS: specific gas constant k_b/(mu m_u), radiation constant
+    R inv_arad;  // 1 / arad (inf for arad = 0)
 };
 
 // ---------------------------------------------------------------- gas + radiation EoS
 // Sect. 2.3, eqs. eos_gp_rad_ein and eos_gp_rad: e = rho Rg T/(gamma-1) + arad T^4 and
 // P = rho Rg T + arad T^4 / 3 (FP64).  The temperature follows from e (or from P) by Newton's
 // method started from the smaller of the gas-only and radiation-only temperatures, an upper bound
-// from which the iteration decreases monotonically to the root.  It stops once every lane of the
-// wave has made a correction of at most EOS_NEWTON_TOL of its T (Newton's quadratic convergence,
-// with (f''/2f') T <= 3/2 for these residuals, then leaves a relative error below 2e-16), and
-// after EOS_NEWTON_STEPS steps at the latest.
+// from which the iteration decreases monotonically to the root (the start is formed with the
+// hardware reciprocal and square root, so it may sit a few ulps below the root; the first step
+// then lands above it, second-order close, and the descent continues).  It stops once every lane
+// of the wave has made a correction of at most EOS_NEWTON_TOL of its T (Newton's quadratic
+// convergence, with (f''/2f') T <= 3/2 for these residuals, then leaves a relative error below
+// 2e-16), and after EOS_NEWTON_STEPS steps at the latest.
 constexpr int EOS_NEWTON_STEPS = 10;
 constexpr double EOS_NEWTON_TOL = 1e-8;
 
@@ -56,13 +59,18 @@ template <bool FROM_P, int K>
 __device__ __forceinline__ void temp_solve(const Gas<double>& g, const double* rho, const double* x, double* T)
 {
     // residual f(T) = c T + a T^4 - y with (c, y) = (rho Rg/(gamma-1), e), or three times the
-    // pressure residual, (3 rho Rg, 3 P): the same root, and no division by 3 in the loop
+    // pressure residual, (3 rho Rg, 3 P): the same root, and no division by 3 in the loop.
+    // Start: T_gas = y/c (reciprocal with one refinement) and T_rad = (y'/a)^(1/4) with y' = e or
+    // 3P (two hardware square roots); inv_arad = inf for a = 0 leaves T_gas
     double c[K], y[K];
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        const double cg = FROM_P ? rho[j] * g.Rg : (rho[j] * g.Rg) / g.gm1;
-        const double tg = x[j] / cg;
-        const double tr = FROM_P ? sqrt(sqrt((3.0 * x[j]) / g.arad)) : sqrt(sqrt(x[j] / g.arad));
+        const double cg = FROM_P ? rho[j] * g.Rg : (rho[j] * g.Rg) * g.inv_gm1;
+        double rc = __builtin_amdgcn_rcp(cg);
+        rc = fma(rc, fma(-cg, rc, 1.0), rc);
+        const double tg = x[j] * rc;
+        const double q = (FROM_P ? 3.0 * x[j] : x[j]) * g.inv_arad;
+        const double tr = __builtin_amdgcn_sqrt(__builtin_amdgcn_sqrt(q));
         T[j] = tg < tr ? tg : tr;
         c[j] = FROM_P ? 3.0 * cg : cg;
         y[j] = FROM_P ? 3.0 * x[j] : x[j];
