@@ -367,6 +367,41 @@ void build_geometry(hx_ctx* x, std::vector<double>& h, std::vector<std::pair<siz
     push(x->L.xfaces, x->faces[0]);
 }
 
+// Build the geometry tables and queue their upload on the context's stream.  Tables whose slots
+// follow each other in the workspace (only alignment padding between them) go up in one copy,
+// the padding as zeros: two copies in all (the tables, the axis-0 faces).  The staging vector
+// stays alive in the context for the asynchronous copies.
+hipError_t upload_geometry(hx_ctx* x)
+{
+    std::vector<double> h;
+    std::vector<std::pair<size_t, size_t>> spans;  // (workspace byte offset, first element in h)
+    build_geometry(x, h, spans);
+    std::vector<double>& img = x->host_tabs;
+    img.clear();
+    std::vector<std::pair<size_t, size_t>> runs;  // (workspace byte offset, first element in img)
+    size_t run_end = 0;
+    for (size_t s = 0; s < spans.size(); s++) {
+        const size_t beg = spans[s].second;
+        const size_t end = s + 1 < spans.size() ? spans[s + 1].second : h.size();
+        const size_t off = spans[s].first;
+        if (runs.empty() || off < run_end || off - run_end >= ALIGN)
+            runs.push_back({off, img.size()});
+        else
+            img.insert(img.end(), (off - run_end) / sizeof(double), 0.0);
+        img.insert(img.end(), h.begin() + beg, h.begin() + end);
+        run_end = off + sizeof(double) * (end - beg);
+    }
+    for (size_t r = 0; r < runs.size(); r++) {
+        const size_t beg = runs[r].second;
+        const size_t end = r + 1 < runs.size() ? runs[r + 1].second : img.size();
+        const hipError_t e = hipMemcpyAsync(x->ws + runs[r].first, img.data() + beg, sizeof(double) * (end - beg),
+                                            hipMemcpyHostToDevice, x->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 hx::Geo geo_of(hx_ctx* x)
 {
     hx::Geo g;
@@ -562,13 +597,8 @@ hx_status hx_create(const hx_config* cfg, void* d_workspace, size_t workspace_by
     x->state[0] = x->ws + L.state[0];
     x->state[1] = x->ws + L.state[1];
     x->geo = geo_of(x);
-    std::vector<std::pair<size_t, size_t>> spans;
-    build_geometry(x, x->host_tabs, spans);
-    for (size_t s = 0; s < spans.size(); s++) {
-        const size_t beg = spans[s].second;
-        const size_t end = s + 1 < spans.size() ? spans[s + 1].second : x->host_tabs.size();
-        hipError_t e = hipMemcpyAsync(x->ws + spans[s].first, x->host_tabs.data() + beg,
-                                      sizeof(double) * (end - beg), hipMemcpyHostToDevice, x->stream);
+    {
+        const hipError_t e = upload_geometry(x);
         if (e != hipSuccess) {
             delete x;
             return fail(HX_EHIP, "geometry upload failed: %s", hipGetErrorString(e));
@@ -624,15 +654,7 @@ hx_status hx_shift_grid(hx_ctx* x, double delta)
     HIPCHECK(hipStreamSynchronize(x->stream));
     for (double& v : f)
         v += delta;
-    x->host_tabs.clear();
-    std::vector<std::pair<size_t, size_t>> spans;
-    build_geometry(x, x->host_tabs, spans);
-    for (size_t s = 0; s < spans.size(); s++) {
-        const size_t beg = spans[s].second;
-        const size_t end = s + 1 < spans.size() ? spans[s + 1].second : x->host_tabs.size();
-        HIPCHECK(hipMemcpyAsync(x->ws + spans[s].first, x->host_tabs.data() + beg, sizeof(double) * (end - beg),
-                                hipMemcpyHostToDevice, x->stream));
-    }
+    HIPCHECK(upload_geometry(x));
     return HX_OK;
 }
 

@@ -5,8 +5,11 @@
 // cell), with the measure dx (Cartesian) or r^2 dr (spherical; the angular factor is common to the
 // row), over its new volume.  Beyond the grid the boundary images supply the state.  A cell whose
 // result is not physical takes the piecewise-constant remap, a convex combination of old cells.
-// One thread per new cell; FP64 arithmetic in the oracle's order (the FP32 form converts on load
-// and store).  Built with -ffp-contract=off.
+// One thread per new cell; FP64 arithmetic (the FP32 form converts on load and store), built with
+// -ffp-contract=off.  Spherical measures are taken without their common factor 1/3 (b^3 - a^3 and
+// (3/4)(b^4 - a^4)), which cancels in content / volume and in the centroids; the slopes and the
+// final average multiply by reciprocals formed once per cell (the centroid spacings are common to
+// every field), so a cell costs 8 FP64 divisions.
 #include <hip/hip_runtime.h>
 
 #include "hx_launch.h"
@@ -17,14 +20,17 @@ namespace {
 
 constexpr int SB = 256;
 
+// measure of [a, b] up to a factor common to the grid (only ratios of measures enter the remap):
+// b - a (Cartesian), b^3 - a^3 = 3 x the integral of r^2 dr (spherical)
 __device__ __forceinline__ double m0_of(int sph, double a, double b)
 {
-    return sph ? (b * b * b - a * a * a) / 3.0 : b - a;
+    return sph ? b * b * b - a * a * a : b - a;
 }
 
+// first moment of [a, b] in the same scale as m0_of
 __device__ __forceinline__ double m1_of(int sph, double a, double b)
 {
-    return sph ? (b * b * b * b - a * a * a * a) / 4.0 : 0.5 * (b * b - a * a);
+    return sph ? 0.75 * (b * b * b * b - a * a * a * a) : 0.5 * (b * b - a * a);
 }
 
 __device__ __forceinline__ double minmod_d(double a, double b)
@@ -106,14 +112,19 @@ __global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p)
         w0[j] = has ? m0_of(p.sph, lo, hi) : 0.0;
         w1[j] = has ? m1_of(p.sph, lo, hi) : 0.0;
     }
+    // reciprocal centroid spacings of the slope stencils, common to every field
+    double idc[3];
+#pragma unroll
+    for (int s = 0; s < 3; s++)
+        idc[s] = 1.0 / (cm[s + 1] - cm[s]);
     // content of field v under the new cell: with the linear profiles, and with constant ones
     auto content = [&](int v, double& lin, double& con) {
         lin = 0.0;
         con = 0.0;
 #pragma unroll
         for (int j = 0; j < 2; j++) {
-            const double sl = minmod_d((q[j + 1][v] - q[j][v]) / (cm[j + 1] - cm[j]),
-                                       (q[j + 2][v] - q[j + 1][v]) / (cm[j + 2] - cm[j + 1]));
+            const double sl = minmod_d((q[j + 1][v] - q[j][v]) * idc[j],
+                                       (q[j + 2][v] - q[j + 1][v]) * idc[j + 1]);
             lin += q[j + 1][v] * w0[j] + sl * (w1[j] - cm[j + 1] * w0[j]);
             con += q[j + 1][v] * w0[j];
         }
@@ -128,11 +139,12 @@ __global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p)
         content(NV - 1, el, c5);
     const double m2 = h[1] * h[1] + h[2] * h[2] + h[3] * h[3];
     const bool ok = h[0] > 0.0 && 2.0 * h[0] * h[4] - m2 > 0.0 && el > 0.0;
+    const double ivnew = 1.0 / vnew;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         double lin, con;
         content(v, lin, con);
-        Un[(long long)v * ncell + c] = (R)((ok ? lin : con) / vnew);
+        Un[(long long)v * ncell + c] = (R)((ok ? lin : con) * ivnew);
     }
 }
 
