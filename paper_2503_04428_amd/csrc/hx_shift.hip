@@ -63,18 +63,21 @@ __device__ __forceinline__ int image0(int i, int n, int lo, int hi, bool& flip)
     return i;
 }
 
+// The grid holds bpr = ceil(n0 / SB) workgroups per (j, k) row of axis 0, so a thread's row and
+// index follow from one wave-uniform division of the workgroup index (no per-thread 64-bit modulo).
 template <typename R, int NV>
-__global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p)
+__global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p, unsigned bpr)
 {
     const long long ncell = p.plane;
-    const long long c = (long long)blockIdx.x * SB + threadIdx.x;
-    if (c >= ncell)
+    const unsigned row = blockIdx.x / bpr;
+    const int i = (int)((blockIdx.x - row * bpr) * SB + threadIdx.x);
+    const int n = p.n0;
+    if (i >= n)
         return;
+    const long long rowoff = (long long)row * n;  // first cell of this (j, k) row
+    const long long c = rowoff + i;
     const R* __restrict__ U = (const R*)p.U;
     R* __restrict__ Un = (R*)p.Unew;
-    const int n = p.n0;
-    const int i = (int)(c % n);
-    const long long rowoff = c - i;  // first cell of this (j, k) row
     const double* xf = p.xf + p.ng;  // xf[i]: face i of axis 0, ghost faces at negative indices
     const double a = xf[i] + p.delta, b = xf[i + 1] + p.delta;
     const double vnew = m0_of(p.sph, a, b);
@@ -151,14 +154,20 @@ __global__ void __launch_bounds__(SB) shift_kernel(const ShiftParams p)
 template <typename R>
 hipError_t go_shift(const ShiftParams& p, hipStream_t s)
 {
-    const unsigned nb = (unsigned)((p.plane + SB - 1) / SB);
+    if (p.n0 < 1 || p.plane % p.n0 != 0)
+        return hipErrorInvalidValue;
+    const unsigned bpr = (unsigned)((p.n0 + SB - 1) / SB);
+    const long long rows = p.plane / p.n0;
+    if (rows * bpr > 0x7fffffffLL)
+        return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)(rows * bpr);
     switch (p.nvar) {
-    case 5: shift_kernel<R, 5><<<nb, SB, 0, s>>>(p); break;
-    case 6: shift_kernel<R, 6><<<nb, SB, 0, s>>>(p); break;
-    case 7: shift_kernel<R, 7><<<nb, SB, 0, s>>>(p); break;
-    case 8: shift_kernel<R, 8><<<nb, SB, 0, s>>>(p); break;
-    case 9: shift_kernel<R, 9><<<nb, SB, 0, s>>>(p); break;
-    case 10: shift_kernel<R, 10><<<nb, SB, 0, s>>>(p); break;
+    case 5: shift_kernel<R, 5><<<nb, SB, 0, s>>>(p, bpr); break;
+    case 6: shift_kernel<R, 6><<<nb, SB, 0, s>>>(p, bpr); break;
+    case 7: shift_kernel<R, 7><<<nb, SB, 0, s>>>(p, bpr); break;
+    case 8: shift_kernel<R, 8><<<nb, SB, 0, s>>>(p, bpr); break;
+    case 9: shift_kernel<R, 9><<<nb, SB, 0, s>>>(p, bpr); break;
+    case 10: shift_kernel<R, 10><<<nb, SB, 0, s>>>(p, bpr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
