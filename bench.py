@@ -241,7 +241,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU domain decomposition is a design, not part of this build)", file=sys.stderr)
+              "(the multi-GPU domain decomposition exists as a design, not as code)", file=sys.stderr)
         sys.exit(2)
     if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
         print("bench.py runs as a single process on one GPU", file=sys.stderr)
