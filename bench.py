@@ -206,15 +206,17 @@ def cpu_baseline(prob, nz_slab):
     o = O.Oracle(prob)
     dt, _ = o.compute_dt(prob.U0)
     n = prob.n
+    nz_slab = min(nz_slab, n[2])
     z0 = n[2] // 2 - nz_slab // 2
     lo, hi = (0, 0, z0), (n[0], n[1], z0 + nz_slab)
     t0 = time.perf_counter()
     _, st = o.step_box(prob.U0, dt, lo, hi)
     el = time.perf_counter() - t0
     cells = n[0] * n[1] * nz_slab
+    what = (f"the whole first step of the {n[0]}x{n[1]}x{n[2]} Sedov state" if nz_slab == n[2] else
+            f"one step of the {n[0]}x{n[1]}x{nz_slab} central slab of the {n[0]}x{n[1]}x{n[2]} Sedov state")
     return {"value": cells / el, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"one step of the {n[0]}x{n[1]}x{nz_slab} central slab of the {n[0]}x{n[1]}x{n[2]} "
-                      f"Sedov state ({cells} cells, {el:.1f} s)"}
+            "sample": f"{what} ({cells} cells, {el:.1f} s)"}
 
 
 def main():
@@ -231,7 +233,8 @@ def main():
                          "measure the other workloads")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--zchunk", type=int, default=None)
-    ap.add_argument("--cpu-slab", type=int, default=96, help="z planes of the oracle's timed slab (0: skip)")
+    ap.add_argument("--cpu-slab", type=int, default=256,
+                    help="z planes of the oracle's timed slab (0: skip; the default times the whole first step)")
     ap.add_argument("--learned-steps", type=int, default=100,
                     help="timed steps of the learned-limiter comparison (0: skip)")
     ap.add_argument("--learned-n", type=int, default=256)
