@@ -21,12 +21,18 @@
 namespace hx {
 
 // Minimum waves per SIMD the register allocator must allow (launch-bound hint).  More waves hide
-// more latency but may force register spills.  FP32 sweeps: HX_MINW_FP32.  FP64 3D sweeps: two
-// waves up to HX_MINW2_FP64_NV fields (measured on the 256^3 workloads: 5 fields 1.47 vs 1.98 ms,
-// 6 fields 1.42 vs 1.46 ms), one wave above (7 fields need ~330 registers); an explicit
-// HX_MINW_FP64 overrides both.
-#ifndef HX_MINW_FP32
-#define HX_MINW_FP32 3
+// more latency but may force register spills.  FP32 3D sweeps: three waves, two where three would
+// spill heavily: spherical sweeps from HX_MINW2_FP32_SPH_NV fields, Cartesian ones from
+// HX_MINW2_FP32_CART_NV (256x128x128, fixed and run-time variants: 9 spherical fields 0.82 vs
+// 0.47 ms, 9 Cartesian 0.58 vs 0.42 ms, 7 Cartesian 0.35 vs 0.36 ms); the learned form keeps three
+// (1.48 vs 1.70 ms); HX_MINW_FP32 overrides the rule.  FP64 3D sweeps: two waves up to
+// HX_MINW2_FP64_NV fields (measured on the 256^3 workloads: 5 fields 1.47 vs 1.98 ms, 6 fields 1.42
+// vs 1.46 ms), one wave above (7 fields need ~330 registers); an explicit HX_MINW_FP64 overrides both.
+#ifndef HX_MINW2_FP32_SPH_NV
+#define HX_MINW2_FP32_SPH_NV 6
+#endif
+#ifndef HX_MINW2_FP32_CART_NV
+#define HX_MINW2_FP32_CART_NV 8
 #endif
 #ifndef HX_MINW2_FP64_NV
 #define HX_MINW2_FP64_NV 6
@@ -35,7 +41,7 @@ namespace hx {
 #ifndef HX_RESLOPE_FP64
 #define HX_RESLOPE_FP64 0
 #endif
-template <typename R, int NV, int NDIM, int SPEC>
+template <typename R, int NV, int NDIM, int GEOM, int SPEC>
 struct MinWaves {
 #ifdef HX_MINW_FP64
     static constexpr int fp64 = HX_MINW_FP64;
@@ -44,7 +50,13 @@ struct MinWaves {
     // at two waves even with 5 or 6 fields)
     static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV && SPEC < 3 ? 2 : 1;
 #endif
-    static constexpr int value = sizeof(R) == 8 ? fp64 : HX_MINW_FP32;
+#ifdef HX_MINW_FP32
+    static constexpr int fp32 = HX_MINW_FP32;
+#else
+    static constexpr int fp32 =
+        NDIM == 3 && SPEC != 2 && NV >= (GEOM == HX_SPH ? HX_MINW2_FP32_SPH_NV : HX_MINW2_FP32_CART_NV) ? 2 : 3;
+#endif
+    static constexpr int value = sizeof(R) == 8 ? fp64 : fp32;
 };
 
 template <int NDIM>
@@ -156,7 +168,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // TAG only separates otherwise identical instantiations built in different units (with different
 // code-generation options), so that each unit launches its own.
 template <typename R, int NV, int NDIM, int GEOM, int SPEC, int TAG = 0>
-__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, SPEC>::value))
+__global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, GEOM, SPEC>::value))
     sweep_kernel(const SweepParams p)
 {
     using N = Num<R>;
