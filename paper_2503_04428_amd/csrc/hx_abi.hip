@@ -512,7 +512,7 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
         if (x->fp32)
             return spec ? hx::launch_sweep_fp32_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream, occ)
                         : hx::launch_sweep_fp32_generic(p, c.ndim, x->nvar, c.geom, x->stream, occ);
-        if (spec && c.ndim == 3 && x->nvar >= 7)
+        if (spec && c.ndim == 3 && x->nvar >= 6)
             return hx::launch_sweep_fp64_3d_ilp(p, 1, x->nvar, c.geom, x->stream, occ);
         return spec ? hx::launch_sweep_fp64_hllc_vl(p, c.ndim, x->nvar, c.geom, x->stream, occ)
                     : hx::launch_sweep_fp64_generic(p, c.ndim, x->nvar, c.geom, x->stream, occ);

@@ -26,8 +26,11 @@ namespace hx {
 // HX_MINW2_FP32_CART_NV (256x128x128, fixed and run-time variants: 9 spherical fields 0.82 vs
 // 0.47 ms, 9 Cartesian 0.58 vs 0.42 ms, 7 Cartesian 0.35 vs 0.36 ms); the learned form keeps three
 // (1.48 vs 1.70 ms); HX_MINW_FP32 overrides the rule.  FP64 3D sweeps: two waves up to
-// HX_MINW2_FP64_NV fields (measured on the 256^3 workloads: 5 fields 1.47 vs 1.98 ms, 6 fields 1.42
-// vs 1.46 ms), one wave above (7 fields need ~330 registers); an explicit HX_MINW_FP64 overrides both.
+// HX_MINW2_FP64_NV fields in Cartesian sweeps and in spherical sweeps with HLLC + van Leer compiled
+// in, one wave otherwise (two vs one, 256x128x128: Cartesian 5 fields 0.50 vs 0.59 ms, 6 fields
+// 0.74 vs 0.70 ms, RT 128x128x512 with 6 fields 1.37 vs 1.31 ms; spherical 5 fields 0.64 vs 0.67
+// ms fixed, 0.93 vs 0.76 ms run-time variant, 6 fields 1.02 vs 0.78 ms; 7 fields need ~330
+// registers); an explicit HX_MINW_FP64 overrides the rule.
 #ifndef HX_MINW2_FP32_SPH_NV
 #define HX_MINW2_FP32_SPH_NV 6
 #endif
@@ -35,7 +38,7 @@ namespace hx {
 #define HX_MINW2_FP32_CART_NV 8
 #endif
 #ifndef HX_MINW2_FP64_NV
-#define HX_MINW2_FP64_NV 6
+#define HX_MINW2_FP64_NV 5
 #endif
 // FP64 sweeps: form the limited slopes again for the face states (1) or hold them (0)
 #ifndef HX_RESLOPE_FP64
@@ -48,7 +51,8 @@ struct MinWaves {
 #else
     // (the internal-energy monitor's extra state and the gas + radiation EoS's Newton solves spill
     // at two waves even with 5 or 6 fields)
-    static constexpr int fp64 = NDIM == 3 && NV <= HX_MINW2_FP64_NV && SPEC < 3 ? 2 : 1;
+    static constexpr int fp64 =
+        NDIM == 3 && NV <= HX_MINW2_FP64_NV && (GEOM == HX_CART ? SPEC < 3 : SPEC == 1) ? 2 : 1;
 #endif
 #ifdef HX_MINW_FP32
     static constexpr int fp32 = HX_MINW_FP32;
