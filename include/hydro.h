@@ -87,8 +87,9 @@ typedef struct {
     int eos;                /* HX_EOS_GAS: ideal gas (eq. eos_gas).  HX_EOS_GAS_RAD: ideal gas plus
                                radiation (Sect. 2.3, eqs. eos_gp_rad_ein and eos_gp_rad:
                                e = rho R T/(gamma-1) + a T^4, P = rho R T + a T^4/3; T from e or P by
-                               ten Newton steps from the smaller of the gas-only and radiation-only
-                               temperatures; sound speed of eq. cs_gp_rad; with dual_energy the
+                               Newton's method from the smaller of the gas-only and radiation-only
+                               temperatures, run until the correction is at most 1e-8 of T (ten
+                               steps at most); sound speed of eq. cs_gp_rad; with dual_energy the
                                monitor's P is the EoS pressure of (rho, e)); needs FP64 and a
                                limiter other than the learned one */
     double eos_R;           /* HX_EOS_GAS_RAD: specific gas constant k_b/(mu m_u), > 0 */
