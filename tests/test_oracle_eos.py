@@ -124,3 +124,31 @@ def test_strong_radiation_shock_compresses_seven_times():
     assert len(plateau) > 40
     med = np.median(plateau[5:-5])
     assert med == pytest.approx(7.0, rel=0.03), med
+
+
+@pytest.mark.parametrize("rho", [1e-8, 1e-4, 1e4, 1e8])
+@pytest.mark.parametrize("T", [1e-5, 1e-3, 0.3, 2.5, 1e3, 1e5])
+def test_converged_temperature_over_wide_ranges(rho, T):
+    """Newton stops once a correction is at most 1e-8 of T (ten steps at most): across sixteen
+    decades of density and ten of temperature, from deeply gas- to deeply radiation-dominated and
+    through the crossover where the start is farthest from the root, the stopped iterate is the
+    root to rounding, from e and from P."""
+    o = _oracle()
+    e = _e_of(rho, T)
+    Tn, Pn, _ = o.eos_state(rho, e)
+    assert Tn == pytest.approx(T, rel=4e-15)
+    assert Pn == pytest.approx(_p_of(rho, T), rel=4e-15)
+    assert o.eos_energy(rho, _p_of(rho, T)) == pytest.approx(e, rel=4e-15)
+
+
+def test_crossover_start_needs_several_steps():
+    """At P_r = P_g the start min(T_gas, T_rad) is 2^(1/4) T above the root (from P); the stopped
+    iterate must still be the root, so the convergence test cannot stop after the first step."""
+    o = _oracle()
+    rho = 1.0
+    T = (3.0 * rho * R / A) ** (1.0 / 3.0)  # rho R T = a T^4 / 3
+    P = _p_of(rho, T)
+    assert rho * R * T == pytest.approx(A * T ** 4 / 3, rel=1e-14)
+    assert o.eos_energy(rho, P) == pytest.approx(_e_of(rho, T), rel=4e-15)
+    Tn, Pn, _ = o.eos_state(rho, _e_of(rho, T))
+    assert Tn == pytest.approx(T, rel=4e-15)
