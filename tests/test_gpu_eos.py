@@ -54,7 +54,25 @@ def _pr_over_pg(pr):
     return out
 
 
+def _wide_range1d(n=400):
+    """A 1D periodic state in pressure balance (P = 1, small velocity) whose density spans eight
+    decades (1e-4 .. 1e4, smoothly): the temperature solves run from deeply gas-dominated cells
+    through the crossover to radiation-dominated ones, where the Newton start is farthest from the
+    root."""
+    pr = P.random_periodic(n=(n,), ndim=1, nscalar=1, seed=57)
+    x = (np.arange(n) + 0.5) / n
+    rho = 10.0 ** (4.0 * np.sin(2.0 * np.pi * x))
+    u = 0.01 * np.sin(4.0 * np.pi * x)
+    U = np.zeros_like(pr.U0)
+    U[0, 0, 0] = rho
+    U[1, 0, 0] = rho * u
+    U[4, 0, 0] = 1.0 / (pr.gamma - 1.0) + 0.5 * rho * u * u
+    U[5, 0, 0] = rho * (0.5 + 0.5 * np.cos(2.0 * np.pi * x))
+    return P.with_gas_rad(pr.with_(U0=U), arad=30.0)
+
+
 CASES = {
+    "wide_range1d": (lambda: _wide_range1d(), 40, None),
     "rad_wall1d_strong": (lambda: P.rad_wall1d(n=200, u0=-100.0), 60, None),
     "sod1d_hll_minmod": (lambda: P.with_gas_rad(P.sod(n=300, limiter="minmod", riemann="hll"), arad=3.0), 60, None),
     "sod1d_arad0": (lambda: P.with_gas_rad(P.sod(n=150), arad=0.0), 40, None),
@@ -129,6 +147,8 @@ def test_cases_span_both_regimes():
     c = _pr_over_pg(CASES["sedov3d_24"][0]())
     assert c.min() < 1e-10 and c.max() > 10.0  # cold ambient gas, radiation-dominated blast
     assert np.all(_pr_over_pg(CASES["rad_wall1d_strong"][0]()) == pytest.approx(10.0, rel=1e-12))
+    w = _pr_over_pg(CASES["wide_range1d"][0]())
+    assert w.min() < 1e-6 and w.max() > 1e3 and np.any((w > 0.3) & (w < 3.0))
 
 
 def test_gas_rad_full_size_sedov_sampled(H):
