@@ -200,11 +200,33 @@ __global__ void __launch_bounds__(RB) shell_partial_kernel(const ShellParams p)
     const long long r1 = rows * (blockIdx.y + 1) / gridDim.y;
     double s = 0.0;
     const double vr = p.geo.vr[i];
-    for (long long r = r0; r < r1; r++) {
-        const int j = (int)(r % p.n[1]);
-        const int k = (int)(r / p.n[1]);
-        const double dV = vr * p.geo.ct[j] * p.geo.w[2][k + (p.ndim > 2 ? p.ng : 0)];
+    const int n1 = p.n[1], kofs = p.ndim > 2 ? p.ng : 0;
+    int j = (int)(r0 % n1), k = (int)(r0 / n1);  // row r = k n1 + j, advanced incrementally
+    long long r = r0;
+    // rows in batches of eight: their loads are issued together, the sum stays in row order
+    constexpr int B = 8;
+    for (; r + B <= r1; r += B) {
+        double x[B], dv[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            dv[b] = vr * p.geo.ct[j] * p.geo.w[2][k + kofs];
+            x[b] = (double)rho[(r + b) * p.n[0] + i];
+            if (++j == n1) {
+                j = 0;
+                k++;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            s += x[b] * dv[b];
+    }
+    for (; r < r1; r++) {
+        const double dV = vr * p.geo.ct[j] * p.geo.w[2][k + kofs];
         s += (double)rho[r * p.n[0] + i] * dV;
+        if (++j == n1) {
+            j = 0;
+            k++;
+        }
     }
     p.partial[(long long)blockIdx.y * p.n[0] + i] = s;
 }
@@ -215,15 +237,31 @@ __global__ void __launch_bounds__(RB) shell_final_kernel(const ShellParams p, in
     __shared__ double m[HX_MAX_NR];
     for (int i = threadIdx.x; i < p.n[0]; i += RB) {
         double s = 0.0;
+#pragma unroll 8
         for (int c = 0; c < nchunk; c++)
             s += p.partial[(long long)c * p.n[0] + i];
         m[i] = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // the running sum in shell order; the shells go through registers eight at a time, so the
+        // LDS loads of a batch overlap instead of each waiting behind the previous shell's store
+        constexpr int B = 8;
         double below = 0.0;
-        for (int i = 0; i < p.n[0]; i++) {
-            double mi = m[i];
+        int i = 0;
+        for (; i + B <= p.n[0]; i += B) {
+            double v[B];
+#pragma unroll
+            for (int j = 0; j < B; j++)
+                v[j] = m[i + j];
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                m[i + j] = p.scale * (below + 0.5 * v[j]);
+                below += v[j];
+            }
+        }
+        for (; i < p.n[0]; i++) {
+            const double mi = m[i];
             m[i] = p.scale * (below + 0.5 * mi);
             below += mi;
         }
