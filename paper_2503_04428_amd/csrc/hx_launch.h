@@ -62,7 +62,7 @@ hipError_t launch_sweep_fp32_mlp(const SweepParams& p, int ndim, int nvar, int g
 hipError_t launch_sweep_fp64_de(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_sweep_fp64_rad(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_sweep_fp64_de_rad(const SweepParams& p, int ndim, int nvar, int geom, hipStream_t s, int* occ);
-// 3D one-wave-per-SIMD instantiations of variants 1 (7-9 fields) and 4 (5-9 fields), scheduled for ILP
+// 3D one-wave-per-SIMD instantiations of variants 1 (6-9 fields) and 4 (5-9 fields), scheduled for ILP
 hipError_t launch_sweep_fp64_3d_ilp(const SweepParams& p, int spec, int nvar, int geom, hipStream_t s, int* occ);
 hipError_t launch_dt_final(const double* partial, int nb, double cfl, double* dt_out, hipStream_t s);
 hipError_t launch_dt(const DtParams& p, bool fp32, int nblocks, double cfl, double* dt_out, hipStream_t s);
