@@ -526,7 +526,8 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
         if (occ < 1 || cus < 1)
             return fail(HX_EHIP, "the sweep does not fit on a compute unit (occupancy %d)", occ);
         const dim3 g = hx::sweep_grid(3, c.n, 1);
-        x->kz_auto = hx::choose_zchunk(c.n[2], (long long)g.x * g.y, (long long)occ * cus);
+        x->kz_auto = hx::choose_zchunk(c.n[2], (long long)g.x * g.y, (long long)occ * cus,
+                                       c.limiter == HX_LIMITER_MLP ? 8 : 4);
     }
     const int kz = x->kz > 0 ? x->kz : x->kz_auto;
     p.kz = c.ndim == 3 ? (kz < c.n[2] ? kz : c.n[2]) : 1;

@@ -101,11 +101,13 @@ inline long long sweep_nblocks(int ndim, const int n[3], int kz)
 // rounds of a launch, slots = resident workgroups of the whole chip, run one after the other, so
 // the launch costs about rounds * (kz + 3) plane steps.  Tiles differ in cost (the learned
 // limiter's network runs where the flow is monotone, divisions are skipped where it is flat), so
-// at least MIN_ROUNDS rounds are kept for the hardware's dynamic dispatch to even them out.  The kz
-// that minimises the cost under that constraint (the larger on a tie) is taken.
-inline int choose_zchunk(int n2, long long tiles, long long slots)
+// at least min_rounds rounds are kept for the hardware's dynamic dispatch to even them out: 4, and
+// 8 for the learned form, whose tiles differ most (quadrants 256^3: kz 16 in 8 rounds 1.42 ms, kz
+// 32 in 4 rounds 1.48 ms; the FP32 van Leer sweep takes 0.72 ms with either).  The kz that
+// minimises the cost under that constraint (the larger on a tie) is taken.
+inline int choose_zchunk(int n2, long long tiles, long long slots, long long min_rounds = 4)
 {
-    constexpr long long MIN_ROUNDS = 4;
+    const long long MIN_ROUNDS = min_rounds;
     if (slots < 1)
         slots = 1;
     int best = 0;
