@@ -80,7 +80,7 @@ typedef struct {
     double g0[3];
     double G, Mc;
     int dual_energy;        /* 1: the last field is the monitored internal energy e per unit volume
-                               (Sect. 2.4: eq. pressure_fix with -P div(u), and the alpha blend of
+                               (Sect. 2.5: eq. pressure_fix with -P div(u), and the alpha blend of
                                the total- and internal-energy updates); needs FP64, HLLC, a
                                limiter other than the learned one and nscalar <= 3.  0: off */
     double de_eps;          /* the blend criterion epsilon (the paper uses 1e-6), >= 0 */
@@ -94,7 +94,7 @@ typedef struct {
                                limiter other than the learned one */
     double eos_R;           /* HX_EOS_GAS_RAD: specific gas constant k_b/(mu m_u), > 0 */
     double eos_arad;        /* HX_EOS_GAS_RAD: radiation constant a, >= 0 */
-    int ni_heating;         /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.1, eq. heating_ni):
+    int ni_heating;         /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.4, eq. heating_ni):
                                E (and e with dual_energy) gains rho f_Ni h(t) with
                                h = lambda {[Q_Ni (tau_Co/tau_Ni - 1) - Q_Co] exp(-t/tau_Ni)
                                + Q_Co exp(-t/tau_Co)}, lambda = 1/(ni_m (tau_Co - tau_Ni)), taken at

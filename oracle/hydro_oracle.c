@@ -16,7 +16,7 @@
  *      U_new = U + dt/dV (F_L dS_L - F_R dS_R) of Sect. 3.3, plus gravity
  *      (Sect. 2.2) and, in spherical coordinates, the momentum source terms of
  *      Sect. 3.1.2 (eq. source_terms_1 and its theta counterpart), 56Ni decay heating
- *      (Sect. 2.1, eq. heating_ni) and the internal-energy monitor (Sect. 2.4).
+ *      (Sect. 2.4, eq. heating_ni) and the internal-energy monitor (Sect. 2.5).
  *
  * Readings where the paper is silent are stated at the point of use.
  */
@@ -621,7 +621,7 @@ static int ctx_init(Ctx *x, const or_config *c)
     return OR_OK;
 }
 
-/* ---- 56Ni decay heating (Sect. 2.1, eq. heating_ni): the energy source rho f_Ni times
+/* ---- 56Ni decay heating (Sect. 2.4, eq. heating_ni): the energy source rho f_Ni times
  * lambda {[Q_Ni (tau_Co / tau_Ni - 1) - Q_Co] exp(-t / tau_Ni) + Q_Co exp(-t / tau_Co)},
  * lambda = 1 / (56 m_u (tau_Co - tau_Ni)), absorbed locally.  The rate per unit mass of 56Ni: */
 double or_ni_rate(const or_config *c, double t)
@@ -795,7 +795,7 @@ double or_eos_energy(const or_config *c, double rho, double P)
 
 double or_de_alpha(double e, double ek, double eps)
 {
-    /* Sect. 2.4: 1 for e >= eps e_k, (e / (eps e_k))^2 down to eps e_k / 10, 0 below */
+    /* Sect. 2.5: 1 for e >= eps e_k, (e / (eps e_k))^2 down to eps e_k / 10, 0 below */
     const double t = eps * ek;
     if (e >= t)
         return 1.0;
@@ -806,8 +806,10 @@ double or_de_alpha(double e, double ek, double eps)
     return 0.0;
 }
 
-int or_step_box(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
-                double *out)
+/* One step over the interior box [lo, hi).  fb (optional, the box's cell count) receives 1 for
+ * every updated cell whose own half step fell back to first order (step D6 below), else 0. */
+static int step_box(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
+                    double *out, unsigned char *fb)
 {
     Ctx x;
     int st = ctx_init(&x, c);
@@ -835,12 +837,16 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
     double *W = (double *)malloc(sizeof(double) * nv * nw);   /* primitives */
     double *FS = (double *)malloc(sizeof(double) * 6 * nv * np); /* [d][side][v][cell] */
     double *UH = (double *)malloc(sizeof(double) * nv * np);  /* U^n + dU (cell half step) */
-    if (!Q || !W || !FS || !UH) {
-        free(Q); free(W); free(FS); free(UH); free(x.gr);
+    unsigned char *BAD = (unsigned char *)malloc((size_t)np);  /* fallback flag per half-step cell */
+    if (!Q || !W || !FS || !UH || !BAD) {
+        free(Q); free(W); free(FS); free(UH); free(BAD); free(x.gr);
         return OR_ENOMEM;
     }
 
     /* 1-2: boundary images and primitives */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int k = bw.lo[2]; k < bw.lo[2] + bw.ext[2]; k++)
         for (int j = bw.lo[1]; j < bw.lo[1] + bw.ext[1]; j++)
             for (int i = bw.lo[0]; i < bw.lo[0] + bw.ext[0]; i++) {
@@ -857,6 +863,9 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
 
     /* 3-4: reconstruction and the Hancock half step for every cell whose face states feed a
      * flux of the box */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int k = bp.lo[2]; k < bp.lo[2] + bp.ext[2]; k++)
         for (int j = bp.lo[1]; j < bp.lo[1] + bp.ext[1]; j++)
             for (int i = bp.lo[0]; i < bp.lo[0] + bp.ext[0]; i++) {
@@ -943,6 +952,7 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                     if (!positive_state(a) || !positive_state(b))
                         bad = 1;
                 }
+                BAD[ip] = (unsigned char)bad;
                 if (bad) {
                     double q0[MAXV];
                     cons(&x, w, q0);
@@ -970,6 +980,9 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
     /* 5-6: fluxes at the faces of each updated cell, then the conservative update */
     int nonphys = 0;
     long nbo = box_size(&bo);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : nonphys)
+#endif
     for (int k = lo[2]; k < hi[2]; k++)
         for (int j = lo[1]; j < hi[1]; j++)
             for (int i = lo[0]; i < hi[0]; i++) {
@@ -1091,7 +1104,7 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                 if (have_src)
                     for (int v = 0; v < nv; v++)
                         acc[v] += dt * S[v];
-                /* internal energy (Sect. 2.4): e_new = e + alpha d1e + (1 - alpha) d2e, d1e from the
+                /* internal energy (Sect. 2.5): e_new = e + alpha d1e + (1 - alpha) d2e, d1e from the
                  * total energy (E - |m|^2 / (2 rho) of the updated cell), d2e from eq. pressure_fix
                  * (acc above); alpha from e and e_k of the cell at time n (reading) */
                 if (c->dual_energy) {
@@ -1109,14 +1122,29 @@ int or_step_box(const or_config *c, const double *U, double dt, const int lo[3],
                 long io = bidx(&bo, i, j, k);
                 for (int v = 0; v < nv; v++)
                     out[v * nbo + io] = acc[v];
+                if (fb)
+                    fb[io] = BAD[ip];
             }
 
     free(Q);
     free(W);
     free(FS);
     free(UH);
+    free(BAD);
     free(x.gr);
     return nonphys ? OR_ENONPHYS : OR_OK;
+}
+
+int or_step_box(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
+                double *out)
+{
+    return step_box(c, U, dt, lo, hi, out, NULL);
+}
+
+int or_step_box_fb(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
+                   double *out, unsigned char *fb)
+{
+    return step_box(c, U, dt, lo, hi, out, fb);
 }
 
 int or_step(const or_config *c, const double *U, double dt, double *Unew)
@@ -1134,6 +1162,10 @@ int or_compute_dt(const or_config *c, const double *U, double *dt)
         return st;
     double smax = 0.0;
     int bad = 0;
+    /* (a maximum does not depend on the order of its terms: any thread count gives the same dt) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(max : smax) reduction(| : bad)
+#endif
     for (int k = 0; k < x.n[2]; k++)
         for (int j = 0; j < x.n[1]; j++)
             for (int i = 0; i < x.n[0]; i++) {
@@ -1240,7 +1272,8 @@ int or_shift_grid(const or_config *c, const double *U, double delta, double *Une
 
 void or_totals(const or_config *c, const double *U, double *tot)
 {
-    int nv = 5 + c->nscalar;
+    /* every field, the monitored internal energy included */
+    int nv = 5 + c->nscalar + (c->dual_energy ? 1 : 0);
     long plane = (long)c->n[0] * c->n[1] * c->n[2];
     for (int v = 0; v < nv; v++) {
         double s = 0.0;

@@ -2,7 +2,9 @@
  * FP64 CPU oracle for one MUSCL-Hancock step of the HERACLES++ Godunov scheme.
  *
  * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, single-threaded
- * reference that the HIP library is checked against.  Only the test suite,
+ * reference that the HIP library is checked against.  Built with OpenMP (liboracle_omp.so), the
+ * step's cell loops run over z planes in parallel; every cell is computed by the same expressions
+ * and the time step is a maximum, so the results are bit for bit those of the serial build.  Only the test suite,
  * the smoke check and the benchmark's CPU-baseline leg may load it; the
  * product path never does.  It shares no code, header or table with the HIP
  * library.
@@ -10,7 +12,7 @@
  * Units of the paper followed here:
  *   Sect. 2.1 (eqs. continuity, momentum, energy, passive scalar; 56Ni decay heating,
  *   eq. heating_ni), Sect. 2.2 (uniform / point / enclosed-mass gravity), Sect. 2.3 (ideal-gas
- *   and gas + radiation EoS), Sect. 2.4 (internal-energy monitor),
+ *   and gas + radiation EoS), Sect. 2.5 (internal-energy monitor),
  *   Sect. 3.1.1 (mesh, dS, dV), Sect. 3.1.2 (spherical momentum sources,
  *   eq. source_terms_1 and the theta counterpart), Sect. 3.2 (slope-limited
  *   reconstruction, Hancock half step, Godunov update eq. godunov, HLL/HLLC,
@@ -60,14 +62,14 @@ typedef struct {
     double g0[3];
     double G, Mc;
     const double *mlp;        /* OR_MLP_NPARAM weights, W1[32][4] b1 W2[32][32] b2 w3[32] b3 */
-    int dual_energy;          /* 1: the last field is the monitored internal energy e (Sect. 2.4,
+    int dual_energy;          /* 1: the last field is the monitored internal energy e (Sect. 2.5,
                                  eq. pressure_fix); needs HLLC */
     double de_eps;            /* the criterion epsilon of the blend factor alpha (paper: 1e-6) */
     int eos;                  /* OR_EOS_GAS (eq. eos_gas) or OR_EOS_GAS_RAD (eqs. eos_gp_rad_ein,
                                  eos_gp_rad, cs_gp_rad) */
     double eos_R;             /* gas + radiation: specific gas constant k_b / (mu m_u) */
     double eos_arad;          /* gas + radiation: radiation constant a_r */
-    int ni_heating;           /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.1, eq. heating_ni)
+    int ni_heating;           /* 1: 56Ni -> 56Co -> 56Fe decay heating (Sect. 2.4, eq. heating_ni)
                                  added to E (and to e with dual_energy) */
     int ni_scalar;            /* the passive scalar that carries rho f_Ni (0 .. nscalar-1) */
     double ni_Q[2];           /* energy released per decay of 56Ni and of 56Co */
@@ -86,6 +88,12 @@ int or_step(const or_config *c, const double *U, double dt, double *Unew);
 int or_step_box(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
                 double *out);
 
+/* or_step_box that also reports, per updated cell (fb, the box's cell count, layout [k][j][i]),
+ * 1 where the cell's own half-step face states were not all physical and the cell was advanced at
+ * first order (the positivity fallback: zero slopes and no half step), else 0. */
+int or_step_box_fb(const or_config *c, const double *U, double dt, const int lo[3], const int hi[3],
+                   double *out, unsigned char *fb);
+
 /* CFL time step: dt = cfl / max over interior cells of sum_d (|u_d| + c_s)/dx_d. */
 int or_compute_dt(const or_config *c, const double *U, double *dt);
 
@@ -94,7 +102,7 @@ int or_compute_dt(const or_config *c, const double *U, double *dt);
  * layers; spherical: the inner radius stays >= 0), written to Unew.  OR_EINVAL otherwise. */
 int or_shift_grid(const or_config *c, const double *U, double delta, double *Unew);
 
-/* Conserved totals sum_cells U_v dV, one per variable. */
+/* Conserved totals sum_cells U_v dV, one per variable (all nvar, the monitored e included). */
 void or_totals(const or_config *c, const double *U, double *tot);
 
 /* Enclosed mass M_enc(r_i) per radial shell (spherical wedge, Sect. 2.2 eq. internal_gravity). */
@@ -110,7 +118,7 @@ double or_eos_energy(const or_config *c, double rho, double P);
 /* 56Ni decay heating rate per unit mass of 56Ni at time t (eq. heating_ni without rho f_Ni). */
 double or_ni_rate(const or_config *c, double t);
 
-/* Blend factor alpha of the internal-energy monitor (Sect. 2.4) for internal energy e and kinetic
+/* Blend factor alpha of the internal-energy monitor (Sect. 2.5) for internal energy e and kinetic
  * energy e_k (per unit volume) and the criterion eps. */
 double or_de_alpha(double e, double ek, double eps);
 

@@ -13,6 +13,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+OMP_LIB_PATH = os.path.join(HERE, "liboracle_omp.so")  # same source, OpenMP over z planes
 OPCOUNT_LIB_PATH = os.path.join(HERE, "liboracle_opcount.so")
 
 GEOM = {"cart": 0, "sph": 1}
@@ -51,12 +52,16 @@ def lib(path: str = LIB_PATH):
             from . import build_oracle
             if path == LIB_PATH:
                 build_oracle.build()
+            elif path == OMP_LIB_PATH:
+                build_oracle.build(openmp=True)
             elif path == OPCOUNT_LIB_PATH:
                 build_oracle.build_opcount()
         L = C.CDLL(path)
         cp = C.POINTER(OrConfig)
         L.or_step.argtypes = [cp, _DP, C.c_double, _DP]
         L.or_step_box.argtypes = [cp, _DP, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), _DP]
+        L.or_step_box_fb.argtypes = [cp, _DP, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), _DP,
+                                     C.POINTER(C.c_ubyte)]
         L.or_compute_dt.argtypes = [cp, _DP, _DP]
         L.or_totals.argtypes = [cp, _DP, _DP]
         L.or_totals.restype = None
@@ -190,6 +195,25 @@ class Oracle:
         if st == EINVAL:
             raise ValueError("oracle: invalid box or configuration")
         return out, st
+
+    def step_fallback(self, U: np.ndarray, dt: float, lo=None, hi=None, t: float = 0.0):
+        """The step over the box [lo, hi) (default: the whole grid) and the positivity-fallback mask
+        of its cells (1 where the cell's own half step was replaced by first order); returns
+        (Unew, mask [k][j][i] as bool, status)."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
+        lo = (0, 0, 0) if lo is None else lo
+        hi = self.n if hi is None else hi
+        self.cfg.time = float(t)
+        lo3 = (C.c_int * 3)(*[int(v) for v in lo])
+        hi3 = (C.c_int * 3)(*[int(v) for v in hi])
+        ext = [int(hi[d]) - int(lo[d]) for d in range(3)]
+        out = np.empty((self.nvar, ext[2], ext[1], ext[0]))
+        fb = np.zeros((ext[2], ext[1], ext[0]), dtype=np.uint8)
+        st = self._L.or_step_box_fb(self._cfgp(), _ptr(U), float(dt), lo3, hi3, _ptr(out),
+                                    fb.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        if st == EINVAL:
+            raise ValueError("oracle: invalid box or configuration")
+        return out, fb.astype(bool), st
 
     def compute_dt(self, U: np.ndarray) -> tuple[float, int]:
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
@@ -347,6 +371,6 @@ def opcount_step(prob, U: np.ndarray, dt: float) -> dict:
 
 
 def de_alpha(e: float, ek: float, eps: float) -> float:
-    """Blend factor of the internal-energy monitor (Sect. 2.4)."""
+    """Blend factor of the internal-energy monitor (Sect. 2.5)."""
     return lib().or_de_alpha(float(e), float(ek), float(eps))
 

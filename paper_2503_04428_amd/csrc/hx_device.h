@@ -134,7 +134,7 @@ __device__ __forceinline__ double uniform_d(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// 56Ni decay heating per unit mass of 56Ni at time t (Sect. 2.1, eq. heating_ni):
+// 56Ni decay heating per unit mass of 56Ni at time t (Sect. 2.4, eq. heating_ni):
 // lambda {[Q_Ni (tau_Co/tau_Ni - 1) - Q_Co] exp(-t/tau_Ni) + Q_Co exp(-t/tau_Co)},
 // lambda = 1 / (m_Ni (tau_Co - tau_Ni))
 __device__ __forceinline__ double ni_rate(const SweepParams& p, double t)
@@ -279,7 +279,7 @@ __device__ __forceinline__ R kinetic_energy(const R* q)
     return R(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
 }
 
-// blend factor of the internal-energy monitor (Sect. 2.4): 1 for e >= eps e_k,
+// blend factor of the internal-energy monitor (Sect. 2.5): 1 for e >= eps e_k,
 // (e / (eps e_k))^2 down to eps e_k / 10, 0 below
 template <typename R>
 __device__ __forceinline__ R de_alpha(R e, R ek, R eps)

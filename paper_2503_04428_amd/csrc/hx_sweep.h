@@ -166,7 +166,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // SPEC = 1 compiles the common HLLC + van Leer case with both choices fixed; SPEC = 2 the learned
 // limiter with HLLC (slope stencil of half-width 2, BF16 matrix-core network); SPEC = 0 reads the
 // limiter and the Riemann solver from the parameters; SPEC = 3 adds the internal-energy monitor
-// (Sect. 2.4: the last field is e, with eq. pressure_fix and the alpha blend; HLLC, limiter from
+// (Sect. 2.5: the last field is e, with eq. pressure_fix and the alpha blend; HLLC, limiter from
 // the parameters); SPEC = 4 the gas + radiation EoS (Sect. 2.3, FP64; limiter and Riemann solver
 // from the parameters); SPEC = 5 both (the monitor's P through the EoS; HLLC).
 // TAG only separates otherwise identical instantiations built in different units (with different

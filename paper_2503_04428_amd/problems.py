@@ -53,12 +53,12 @@ class Problem:
     t_end: float = 0.0
     nsteps: int = 0
     meta: dict = field(default_factory=dict)
-    dual_energy: bool = False     # last field = monitored internal energy e (Sect. 2.4)
+    dual_energy: bool = False     # last field = monitored internal energy e (Sect. 2.5)
     de_eps: float = 1e-6          # criterion of the blend factor alpha
     eos: str = "gas"              # "gas" (eq. eos_gas) or "gas_rad" (gas + radiation, Sect. 2.3)
     eos_R: float = 0.0            # gas + radiation: specific gas constant k_b / (mu m_u)
     eos_arad: float = 0.0         # gas + radiation: radiation constant
-    ni_heating: bool = False      # 56Ni decay heating (Sect. 2.1, eq. heating_ni)
+    ni_heating: bool = False      # 56Ni decay heating (Sect. 2.4, eq. heating_ni)
     ni_scalar: int = 0            # the passive scalar carrying rho f_Ni
     ni_Q: tuple = (0.0, 0.0)      # energy per decay of 56Ni and 56Co
     ni_tau: tuple = (1.0, 2.0)    # lifetimes of 56Ni and 56Co
@@ -373,6 +373,40 @@ def random_periodic(n=(12, 10, 8), ndim=3, nscalar=2, seed=7, geom="cart", amp=0
                precision=precision)
 
 
+def expansion(n=(32, 1, 1), ndim=1, V=2.0, p0=1e-3, width=3.0, nscalar=0, rho_amp=0.0, seed=9,
+              axis=0, limiter="vanleer", riemann="hllc", ng=GHOSTS_DEFAULT, precision="fp64",
+              bc="transmissive", gamma=1.4) -> Problem:
+    """A cold gas flying apart from the centre of [0,1]^ndim: rho 1 (times 1 + rho_amp U(-1,1),
+    seeded), P p0, outward velocity V tanh(r / (width cells)) along the radius r from the centre
+    (in 1D along x, or along `axis` of a grid whose other axes are inactive-like copies), passive
+    scalars f_s = 1 / (1 + (s + 1) r^2).  Where the expansion is steep and cold, the Hancock half
+    step of a limited reconstruction drives face-state pressures (or densities) negative, so the
+    positivity fallback of the step takes over in those cells."""
+    n = tuple(list(n[:3]) + [1] * (3 - len(n)))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (n[2], n[1], n[0])
+    fs = [uniform_faces(0.0, 1.0, n[d]) if d < ndim else _inactive("cart", d) for d in range(3)]
+    cs = [0.5 * (f[:-1] + f[1:]) - 0.5 if d < ndim else np.zeros(1) for d, f in enumerate(fs)]
+    Z, Y, X = np.meshgrid(cs[2], cs[1], cs[0], indexing="ij")
+    comp = [X, Y, Z]
+    if ndim == 1 and axis != 0:
+        raise ValueError("a 1D expansion runs along axis 0")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    hcell = 1.0 / max(n[d] for d in range(ndim))
+    speed = V * np.tanh(r / (width * hcell))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        u = [np.where(r > 0, speed * comp[d] / r, 0.0) if d < ndim else np.zeros(shape) for d in range(3)]
+    rho = np.ones(shape)
+    if rho_amp:
+        rho = rho * (1.0 + rho_amp * rng.uniform(-1, 1, size=shape))
+    p = np.full(shape, p0)
+    scal = [1.0 / (1.0 + (s + 1) * r * r) for s in range(nscalar)]
+    U = _pack(rho, u[0], u[1], u[2], p, scal, gamma)
+    bcs = [[bc, bc] for _ in range(3)]
+    return _mk("expansion", ndim, "cart", n, fs, ng, bcs, U, nscalar=nscalar, gamma=gamma, cfl=0.5,
+               riemann=riemann, limiter=limiter, precision=precision)
+
+
 def sedov_sph1d(n: int = 400, ng: int = GHOSTS_DEFAULT) -> Problem:
     """1D spherical Sedov (paper App. C.4): r in [0,1], rho 1, E 1e-12 except E1 = 1 in the
     first shell, gamma 1.4, reflective centre, transmissive outer boundary."""
@@ -498,7 +532,7 @@ WORKLOADS = {
 
 
 def with_internal_energy(prob: Problem, eps: float = 1e-6) -> Problem:
-    """The same problem with the internal-energy monitor of Sect. 2.4: one more field, initialised
+    """The same problem with the internal-energy monitor of Sect. 2.5: one more field, initialised
     to e = E - |m|^2 / (2 rho)."""
     U = prob.U0
     e = U[4] - 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0]
@@ -599,7 +633,7 @@ def rad_wall1d(n: int = 400, u0: float = -3.0, R: float = 1.0, arad: float = 30.
 
 
 # 56Ni -> 56Co -> 56Fe in CGS: energies per decay (1.75 and 3.73 MeV, gamma rays and positrons) and
-# lifetimes (8.8 and 111.3 days) as Sect. 2.1 gives them; the mass of a 56Ni nucleus is 56 m_u
+# lifetimes (8.8 and 111.3 days) as Sect. 2.4 gives them; the mass of a 56Ni nucleus is 56 m_u
 MEV_ERG = 1.602176634e-6
 M_U_G = 1.66053906660e-24
 DAY_S = 86400.0
@@ -607,7 +641,7 @@ NI_CGS = dict(ni_Q=(1.75 * MEV_ERG, 3.73 * MEV_ERG), ni_tau=(8.8 * DAY_S, 111.3 
 
 
 def with_ni_heating(prob: Problem, scalar: int = 0, Q=(1.0, 2.0), tau=(0.05, 0.6), m: float = 1.0) -> Problem:
-    """The same problem with 56Ni decay heating (Sect. 2.1, eq. heating_ni): passive scalar `scalar`
+    """The same problem with 56Ni decay heating (Sect. 2.4, eq. heating_ni): passive scalar `scalar`
     carries rho f_Ni.  The defaults are code units in which the decay is fast enough to matter in a
     short run; NI_CGS holds the physical constants."""
     return prob.with_(name=prob.name + "+ni", ni_heating=True, ni_scalar=int(scalar), ni_Q=tuple(Q),

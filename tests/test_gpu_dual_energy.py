@@ -1,4 +1,4 @@
-"""GPU parity of the internal-energy monitor (Sect. 2.4; variant 3 of the fused sweep, FP64)
+"""GPU parity of the internal-energy monitor (Sect. 2.5; variant 3 of the fused sweep, FP64)
 against the FP64 oracle on the same seeded inputs: every geometry and dimension, boundary kinds,
 gravity, ragged z chunks, and blend factors alpha in all three branches.  FP64 bar as for the
 other sweeps: per cell |dU| <= 1e-12 |U_oracle| + 1e-14 max|U_oracle,field|."""

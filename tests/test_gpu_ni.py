@@ -1,4 +1,4 @@
-"""GPU parity of the 56Ni decay heating (Sect. 2.1, eq. heating_ni) against the FP64 oracle on the
+"""GPU parity of the 56Ni decay heating (Sect. 2.4, eq. heating_ni) against the FP64 oracle on the
 same seeded inputs: the ideal-gas sweeps (fixed HLLC + van Leer and run-time choices), the gas +
 radiation EoS, the internal-energy monitor, 1D-3D, Cartesian and spherical, with the decay clock
 advanced on the device by host and device time steps.  Both sides evaluate the decay exponentials

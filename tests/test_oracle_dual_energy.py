@@ -1,4 +1,4 @@
-"""Pins of the oracle's internal-energy monitor (Sect. 2.4, eq. pressure_fix and the blend factor
+"""Pins of the oracle's internal-energy monitor (Sect. 2.5, eq. pressure_fix and the blend factor
 alpha): the blend factor's branches, the two limits of the blend, a passive-scalar identity, and
 second-order agreement of the internal-energy equation with the total-energy equation in a smooth
 flow (which a dropped or sign-flipped P div(u) term would break)."""
@@ -137,3 +137,15 @@ def test_monitor_with_gas_radiation_eos_converges_to_total_energy():
         errs.append(np.mean(np.abs(U[-1] - _eint(U))))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) > 1.7, (errs, rates)
+
+
+def test_totals_cover_the_monitored_internal_energy():
+    # sum_cells U_v dV for every field, the monitored e (the last one) included; on a uniform
+    # Cartesian grid dV is the same for every cell, so the totals are plain sums times dV
+    prob = P.with_internal_energy(P.random_periodic(n=(8, 6, 4), ndim=3, nscalar=1))
+    tot = O.Oracle(prob).totals(prob.U0)
+    dV = (1.0 / 8) * (1.0 / 6) * (1.0 / 4)
+    ref = prob.U0.reshape(prob.nvar, -1).sum(axis=1) * dV
+    assert tot.shape == (prob.nvar,)
+    assert np.allclose(tot, ref, rtol=1e-13, atol=0)
+    assert tot[-1] > 0

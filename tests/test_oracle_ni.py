@@ -1,4 +1,4 @@
-"""Pins of the oracle's 56Ni decay heating (Sect. 2.1, eq. heating_ni): the rate against the
+"""Pins of the oracle's 56Ni decay heating (Sect. 2.4, eq. heating_ni): the rate against the
 decay chain's populations integrated as an ODE (Bateman), its value at t = 0 and its time integral
 (every 56Ni nucleus releases Q_Ni + Q_Co in the end), and the step: a uniform medium at rest gains
 exactly dt h(t + dt/2) rho f_Ni per step, second order in time against the integral; the monitored
