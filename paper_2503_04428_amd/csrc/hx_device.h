@@ -35,66 +35,64 @@ template <typename R>
 struct Gas {
     R gm1, inv_gm1, gamma;
     R Rg, arad;  // gas + radiation EoS: specific gas constant k_b/(mu m_u), radiation constant
-    R inv_arad;  // 1 / arad (inf for arad = 0)
 };
 
 // ---------------------------------------------------------------- gas + radiation EoS
 // Sect. 2.3, eqs. eos_gp_rad_ein and eos_gp_rad: e = rho Rg T/(gamma-1) + arad T^4 and
 // P = rho Rg T + arad T^4 / 3 (FP64).  The temperature follows from e (or from P) by Newton's
 // method started from the smaller of the gas-only and radiation-only temperatures, an upper bound
-// from which the iteration decreases monotonically to the root (the start is formed with the
-// hardware reciprocal and square root, so it may sit a few ulps below the root; the first step
-// then lands above it, second-order close, and the descent continues).  It stops once every lane
-// of the wave has made a correction of at most EOS_NEWTON_TOL of its T (Newton's quadratic
-// convergence, with (f''/2f') T <= 3/2 for these residuals, then leaves a relative error below
-// 2e-16), and after EOS_NEWTON_STEPS steps at the latest.
+// from which the iteration decreases monotonically to the root.  Each lane stops once its own
+// correction is at most EOS_NEWTON_TOL of its T (Newton's quadratic convergence, with
+// (f''/2f') T <= 3/2 for these residuals, then leaves a relative error below 2e-16), and after
+// EOS_NEWTON_STEPS steps at the latest.  Every operation is the IEEE-rounded one of the plain
+// definition (divisions and square roots included, in the same order), so a lane's iterates and
+// its stopping step do not depend on the other lanes of its wave.
 constexpr int EOS_NEWTON_STEPS = 10;
 constexpr double EOS_NEWTON_TOL = 1e-8;
 
 __device__ __forceinline__ double t4(double T) { return (T * T) * (T * T); }
 
 // K independent temperatures in one loop (from e, or from P with FROM_P), so that the dependent
-// chains of their Newton steps overlap
+// chains of their Newton steps overlap; a lane keeps stepping a chain until that chain has met
+// the stopping test
 template <bool FROM_P, int K>
 __device__ __forceinline__ void temp_solve(const Gas<double>& g, const double* rho, const double* x, double* T)
 {
-    // residual f(T) = c T + a T^4 - y with (c, y) = (rho Rg/(gamma-1), e), or three times the
-    // pressure residual, (3 rho Rg, 3 P): the same root, and no division by 3 in the loop.
-    // Start: T_gas = y/c (reciprocal with one refinement) and T_rad = (y'/a)^(1/4) with y' = e or
-    // 3P (two hardware square roots); inv_arad = inf for a = 0 leaves T_gas
-    double c[K], y[K];
+    // from e: f(T) = c T + a T^4 - e, c = rho Rg/(gamma-1); from P: f(T) = c T + a T^4/3 - P,
+    // c = rho Rg.  Start: the smaller of c^-1 e (or c^-1 P) and (e/a)^(1/4) (or (3P/a)^(1/4));
+    // a = 0 gives an infinite radiation-only temperature, so the start is the gas one
+    double c[K];
+    bool act[K];
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        const double cg = FROM_P ? rho[j] * g.Rg : (rho[j] * g.Rg) * g.inv_gm1;
-        double rc = __builtin_amdgcn_rcp(cg);
-        rc = fma(rc, fma(-cg, rc, 1.0), rc);
-        const double tg = x[j] * rc;
-        const double q = (FROM_P ? 3.0 * x[j] : x[j]) * g.inv_arad;
-        const double tr = __builtin_amdgcn_sqrt(__builtin_amdgcn_sqrt(q));
+        c[j] = FROM_P ? rho[j] * g.Rg : (rho[j] * g.Rg) / g.gm1;
+        const double tg = x[j] / c[j];
+        const double tr = sqrt(sqrt(FROM_P ? (3.0 * x[j]) / g.arad : x[j] / g.arad));
         T[j] = tg < tr ? tg : tr;
-        c[j] = FROM_P ? 3.0 * cg : cg;
-        y[j] = FROM_P ? 3.0 * x[j] : x[j];
+        act[j] = true;
     }
-    const double a4 = 4.0 * g.arad;
 #pragma unroll 1
     for (int it = 0; it < EOS_NEWTON_STEPS; it++) {
-        bool done = true;
+        bool more = false;
 #pragma unroll
         for (int j = 0; j < K; j++) {
-            const double Tj = T[j];
-            const double T3 = (Tj * Tj) * Tj;
-            const double f = (c[j] * Tj + g.arad * (T3 * Tj)) - y[j];
-            const double fp = c[j] + a4 * T3;
-            // 1/f' from the hardware reciprocal and one Newton refinement of it: the correction
-            // then carries a relative error far below its own size, and the root of f stays the
-            // fixed point of the iteration
-            double r = __builtin_amdgcn_rcp(fp);
-            r = fma(r, fma(-fp, r, 1.0), r);
-            const double dT = f * r;
-            T[j] = Tj - dT;
-            done = done && fabs(dT) <= EOS_NEWTON_TOL * T[j];
+            if (act[j]) {
+                const double Tj = T[j];
+                double f, fp;
+                if (FROM_P) {
+                    f = c[j] * Tj + (g.arad * t4(Tj)) / 3.0 - x[j];
+                    fp = c[j] + (4.0 * g.arad * ((Tj * Tj) * Tj)) / 3.0;
+                } else {
+                    f = c[j] * Tj + g.arad * t4(Tj) - x[j];
+                    fp = c[j] + 4.0 * g.arad * ((Tj * Tj) * Tj);
+                }
+                const double dT = f / fp;
+                T[j] = Tj - dT;
+                act[j] = !(fabs(dT) <= EOS_NEWTON_TOL * T[j]);
+            }
+            more = more || act[j];
         }
-        if (__all(done))
+        if (!__any(more))
             break;
     }
 }

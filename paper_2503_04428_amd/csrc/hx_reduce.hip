@@ -60,7 +60,6 @@ __global__ void __launch_bounds__(RB) dt_partial_kernel(const DtParams p)
             g.inv_gm1 = 1.0 / p.gm1;
             g.Rg = p.eos_R;
             g.arad = p.eos_arad;
-            g.inv_arad = 1.0 / p.eos_arad;
             const double T = temp_from_e(g, rho, q[4] - ke);
             pr = (rho * g.Rg) * T + (g.arad * t4(T)) / 3.0;
             if (!fin || !(rho > 0.0) || !(pr > 0.0)) {

@@ -260,10 +260,6 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     gas.inv_gm1 = N::from_d(1.0 / (p.gamma - 1.0));
     gas.Rg = N::from_d(p.eos_R);
     gas.arad = N::from_d(p.eos_arad);
-    if constexpr (sizeof(R) == 8)
-        gas.inv_arad = uniform_d(1.0 / p.eos_arad);
-    else
-        gas.inv_arad = N::from_d(1.0 / p.eos_arad);
 
     // images of this thread's x / y indices
     bool fx, fy;
