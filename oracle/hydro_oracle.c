@@ -20,6 +20,9 @@
  *
  * Readings where the paper is silent are stated at the point of use.
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "hydro_oracle.h"
 
 #include <math.h>
@@ -60,6 +63,37 @@ static double xf(const or_config *c, int d, int i)
 
 static double xcen(const or_config *c, int d, int i) { return 0.5 * (xf(c, d, i) + xf(c, d, i + 1)); }
 static double dxc(const or_config *c, int d, int i) { return xf(c, d, i + 1) - xf(c, d, i); }
+
+/* Position of cell i along axis d in the reconstruction with volume centroids (the option
+ * `centroid`, reading of the cell centre r_i of Sect. 3.1 on non-uniform spherical cells): the
+ * centroid of the cell's volume measure along the axis.  Spherical r, measure r^2 dr:
+ * (3/4) (b^4 - a^4) / (b^3 - a^3), written without the cancellation of the differences as
+ * (3/4) (b + a) (b^2 + a^2) / (b^2 + b a + a^2); spherical theta, measure sin(theta) dtheta:
+ * [sin(t) - t cos(t)]_a^b / (cos a - cos b); Cartesian axes and phi (uniform measure): the face
+ * midpoint.  The ghost faces are taken to mirror the interior faces about a non-periodic boundary
+ * face and to repeat them across a periodic one (as the grid generators build them). */
+static double xrec(const or_config *c, int d, int i)
+{
+    if (!c->centroid || c->geom != OR_SPH || d == 2)
+        return xcen(c, d, i);
+    /* a ghost cell is the image of an interior cell (reading 8), so its centroid is the image's,
+     * moved like its faces: mirrored about the boundary face, or translated across a periodic axis */
+    const int n = c->n[d];
+    if (i < 0) {
+        if (c->bc[d][0] == OR_BC_PERIODIC)
+            return xrec(c, d, i + n) - (xf(c, d, n) - xf(c, d, 0));
+        return 2.0 * xf(c, d, 0) - xrec(c, d, -1 - i);
+    }
+    if (i >= n) {
+        if (c->bc[d][1] == OR_BC_PERIODIC)
+            return xrec(c, d, i - n) + (xf(c, d, n) - xf(c, d, 0));
+        return 2.0 * xf(c, d, n) - xrec(c, d, 2 * n - 1 - i);
+    }
+    const double a = xf(c, d, i), b = xf(c, d, i + 1);
+    if (d == 0)
+        return 0.75 * ((b + a) * (b * b + a * a)) / (b * b + b * a + a * a);
+    return ((sin(b) - b * cos(b)) - (sin(a) - a * cos(a))) / (cos(a) - cos(b));
+}
 
 /* physical width of interior cell (i,j,k) along axis d (Sect. 3.1: dr, r dtheta, r sin(theta) dphi) */
 static double width_interior(const or_config *c, int d, int i, int j, int k)
@@ -435,6 +469,47 @@ void or_riemann_flux(int solver, int d, int nvar, double gamma, const double *qL
 
 /* ------------------------------------------------------------------ limiters */
 
+/* Reconstruction coefficients of cell ic along axis d: the face increments are dl at the upper
+ * face and kap dl at the lower one, dl = limiter(cm (w_i - w_{i-1}), cp (w_{i+1} - w_i)).  With
+ * centres at the face midpoints both increments are (dx/2) sigma: cm, cp = (dx/2) over the centre
+ * distances and kap = 1.  With volume centroids x_c they are (x+ - x_c) sigma and (x_c - x-) sigma,
+ * sigma the limited slope over the centroid distances: the limiters are positively homogeneous,
+ * so they act on the differences scaled by the upper extrapolation distance, and kap is the ratio
+ * of the lower distance to the upper one. */
+static void recon_coeffs(const or_config *c, int d, int ic, double *cm, double *cp, double *kap)
+{
+    if (c->centroid && c->geom == OR_SPH && d < 2) {
+        const double xc = xrec(c, d, ic);
+        const double hp = xf(c, d, ic + 1) - xc;
+        *cm = hp / (xc - xrec(c, d, ic - 1));
+        *cp = hp / (xrec(c, d, ic + 1) - xc);
+        *kap = (xc - xf(c, d, ic)) / hp;
+        return;
+    }
+    const double half = 0.5 * dxc(c, d, ic);
+    *cm = half / (xcen(c, d, ic) - xcen(c, d, ic - 1));
+    *cp = half / (xcen(c, d, ic + 1) - xcen(c, d, ic));
+    *kap = 1.0;
+}
+
+/* Upper face increment from the differences dm = w_i - w_{i-1}, dp = w_{i+1} - w_i (the lower one is
+ * kap times it).  About volume centroids an extrapolation distance can exceed half the distance
+ * to the neighbouring centroid (next to r = 0 the centroid sits at 3/4 of the first cell), where
+ * the textbook limiters would carry a face value beyond the neighbouring cell value; there the
+ * increment is also bounded so that both face values stay between the neighbouring cell values:
+ * |dl| <= |dp| and kap |dl| <= |dm| (reading).  With face-midpoint centres the bound never binds
+ * for these limiters on uniform grids, and it is not applied. */
+static double face_increment(const or_config *c, double cm, double cp, double kap, double dm, double dp)
+{
+    double dl = or_limiter(c->limiter, cm * dm, cp * dp);
+    if (c->centroid && c->geom == OR_SPH && dl != 0.0) {
+        const double bound = fmin(fabs(dp), fabs(dm) / kap);
+        if (fabs(dl) > bound)
+            dl = dl > 0.0 ? bound : -bound;
+    }
+    return dl;
+}
+
 /* limited half increment from the two one-sided half increments a, b.  The paper names the
  * limiters (Sect. 3.2) without printing them; these are the textbook forms.  All are
  * positively homogeneous of degree one, so applying them to slopes already scaled by
@@ -586,6 +661,9 @@ static int ctx_init(Ctx *x, const or_config *c)
     if (c->dual_energy && (c->riemann != OR_HLLC || !(c->de_eps >= 0.0)))
         return OR_EINVAL;
     if (c->limiter == OR_LIM_MLP && (c->ng < 3 || !c->mlp))
+        return OR_EINVAL;
+    /* (the learned limiter's TVD test is written for one extrapolation distance per cell) */
+    if (c->centroid && c->limiter == OR_LIM_MLP)
         return OR_EINVAL;
     if (c->ng < 2)
         return OR_EINVAL;
@@ -888,10 +966,8 @@ static int step_box(const or_config *c, const double *U, double dt, const int lo
                     e[d] = 1;
                     long im = bidx(&bw, i - e[0], j - e[1], k - e[2]);
                     long ipp = bidx(&bw, i + e[0], j + e[1], k + e[2]);
-                    int ic = cidx[d];
-                    double half = 0.5 * dxc(c, d, ic);
-                    double cm = half / (xcen(c, d, ic) - xcen(c, d, ic - 1));
-                    double cp = half / (xcen(c, d, ic + 1) - xcen(c, d, ic));
+                    double cm, cp, kap;
+                    recon_coeffs(c, d, cidx[d], &cm, &cp, &kap);
                     double wm[MAXV], wp[MAXV];
                     for (int v = 0; v < nv; v++) {
                         double dl;
@@ -902,11 +978,9 @@ static int step_box(const or_config *c, const double *U, double dt, const int lo
                                             W[v * nw + ipp] - w[v], W[v * nw + ip2] - W[v * nw + ipp]};
                             dl = or_mlp_slope(c->mlp, dd, cm, cp);
                         } else {
-                            double a = cm * (w[v] - W[v * nw + im]);
-                            double b = cp * (W[v * nw + ipp] - w[v]);
-                            dl = or_limiter(c->limiter, a, b);
+                            dl = face_increment(c, cm, cp, kap, w[v] - W[v * nw + im], W[v * nw + ipp] - w[v]);
                         }
-                        wm[v] = w[v] - dl;
+                        wm[v] = w[v] - kap * dl;
                         wp[v] = w[v] + dl;
                     }
                     cons(&x, wm, um[d]);
@@ -1147,6 +1221,33 @@ int or_step_box_fb(const or_config *c, const double *U, double dt, const int lo[
     return step_box(c, U, dt, lo, hi, out, fb);
 }
 
+int or_face_states(const or_config *c, const double *U, int i, int j, int k, int d, double *wm, double *wp)
+{
+    Ctx x;
+    int st = ctx_init(&x, c);
+    if (st)
+        return st;
+    if (d < 0 || d >= 3 || !x.act[d] || c->limiter == OR_LIM_MLP)
+        return OR_EINVAL;
+    int e[3] = {0, 0, 0};
+    e[d] = 1;
+    int cidx[3] = {i, j, k};
+    double q[3][MAXV], w[3][MAXV];
+    for (int s = 0; s < 3; s++) {
+        int fl[3];
+        fetch(&x, U, i + (s - 1) * e[0], j + (s - 1) * e[1], k + (s - 1) * e[2], q[s], fl);
+        prim(&x, q[s], w[s]);
+    }
+    double cm, cp, kap;
+    recon_coeffs(c, d, cidx[d], &cm, &cp, &kap);
+    for (int v = 0; v < x.nvar; v++) {
+        const double dl = face_increment(c, cm, cp, kap, w[1][v] - w[0][v], w[2][v] - w[1][v]);
+        wm[v] = w[1][v] - kap * dl;
+        wp[v] = w[1][v] + dl;
+    }
+    return OR_OK;
+}
+
 int or_step(const or_config *c, const double *U, double dt, double *Unew)
 {
     int lo[3] = {0, 0, 0};
@@ -1154,21 +1255,27 @@ int or_step(const or_config *c, const double *U, double dt, double *Unew)
     return or_step_box(c, U, dt, lo, hi, Unew);
 }
 
-int or_compute_dt(const or_config *c, const double *U, double *dt)
+/* The CFL step of the cells of the box [lo, hi) (the whole grid in or_compute_dt) */
+static int compute_dt_box(const or_config *c, const double *U, const int lo[3], const int hi[3], double *dt)
 {
     Ctx x;
     int st = ctx_init(&x, c);
     if (st)
         return st;
+    for (int d = 0; d < 3; d++)
+        if (lo[d] < 0 || hi[d] > x.n[d] || lo[d] >= hi[d]) {
+            free(x.gr);
+            return OR_EINVAL;
+        }
     double smax = 0.0;
     int bad = 0;
     /* (a maximum does not depend on the order of its terms: any thread count gives the same dt) */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) reduction(max : smax) reduction(| : bad)
 #endif
-    for (int k = 0; k < x.n[2]; k++)
-        for (int j = 0; j < x.n[1]; j++)
-            for (int i = 0; i < x.n[0]; i++) {
+    for (int k = lo[2]; k < hi[2]; k++)
+        for (int j = lo[1]; j < hi[1]; j++)
+            for (int i = lo[0]; i < hi[0]; i++) {
                 double q[MAXV], w[MAXV];
                 int fl[3];
                 fetch(&x, U, i, j, k, q, fl);
@@ -1186,8 +1293,21 @@ int or_compute_dt(const or_config *c, const double *U, double *dt)
                 if (s > smax)
                     smax = s;
             }
+    free(x.gr);
     *dt = c->cfl / smax;
     return bad ? OR_ENONPHYS : OR_OK;
+}
+
+int or_compute_dt(const or_config *c, const double *U, double *dt)
+{
+    const int lo[3] = {0, 0, 0};
+    const int hi[3] = {c->n[0], c->n[1], c->n[2]};
+    return compute_dt_box(c, U, lo, hi, dt);
+}
+
+int or_compute_dt_box(const or_config *c, const double *U, const int lo[3], const int hi[3], double *dt)
+{
+    return compute_dt_box(c, U, lo, hi, dt);
 }
 
 /* ---- grid shift (Sect. 3.1.1, moving grid): every face of axis 0 moves by delta and the state
@@ -1268,6 +1388,16 @@ int or_shift_grid(const or_config *c, const double *U, double delta, double *Une
                     Unew[v * plane + off] = out[ok ? 0 : 1][v] / vnew;
             }
     return OR_OK;
+}
+
+/* threads the step's loops run on: OpenMP's team size in the OpenMP build, 1 in the serial one */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void or_totals(const or_config *c, const double *U, double *tot)

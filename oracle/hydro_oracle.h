@@ -76,6 +76,9 @@ typedef struct {
     double ni_tau[2];         /* lifetimes tau_Ni < tau_Co */
     double ni_m;              /* mass of one 56Ni nucleus (56 m_u) */
     double time;              /* time t^n at the start of the step (the decay clock) */
+    int centroid;             /* 1: reconstruction about the volume centroids of spherical cells
+                                 (r and theta; Cartesian axes and phi keep the face midpoints);
+                                 0: every cell centre at its face midpoint.  Not with the MLP */
 } or_config;
 
 /* Full step of interior U (layout [nvar][n3][n2][n1]) with time step dt into Unew.
@@ -95,7 +98,14 @@ int or_step_box_fb(const or_config *c, const double *U, double dt, const int lo[
                    double *out, unsigned char *fb);
 
 /* CFL time step: dt = cfl / max over interior cells of sum_d (|u_d| + c_s)/dx_d. */
+/* The limited face states (primitives) of cell (i, j, k) along axis d before the half step, as the
+ * step forms them: wm at the lower face, wp at the upper (nvar values each; not for the MLP). */
+int or_face_states(const or_config *c, const double *U, int i, int j, int k, int d, double *wm, double *wp);
 int or_compute_dt(const or_config *c, const double *U, double *dt);
+int or_num_threads(void);
+/* the same over the cells of the box [lo, hi) only (the grid's step where every cell outside the
+ * box has the state of a cell inside it) */
+int or_compute_dt_box(const or_config *c, const double *U, const int lo[3], const int hi[3], double *dt);
 
 /* Grid shift along axis 0 (Sect. 3.1.1, moving grid): the state U on the faces of c, carried
  * conservatively onto the faces moved by delta (|delta| <= the narrowest cell incl. the two ghost

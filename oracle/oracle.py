@@ -37,7 +37,7 @@ class OrConfig(C.Structure):
         ("mlp", _DP), ("dual_energy", C.c_int), ("de_eps", C.c_double),
         ("eos", C.c_int), ("eos_R", C.c_double), ("eos_arad", C.c_double),
         ("ni_heating", C.c_int), ("ni_scalar", C.c_int), ("ni_Q", C.c_double * 2), ("ni_tau", C.c_double * 2),
-        ("ni_m", C.c_double), ("time", C.c_double),
+        ("ni_m", C.c_double), ("time", C.c_double), ("centroid", C.c_int),
     ]
 
 
@@ -63,6 +63,10 @@ def lib(path: str = LIB_PATH):
         L.or_step_box_fb.argtypes = [cp, _DP, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), _DP,
                                      C.POINTER(C.c_ubyte)]
         L.or_compute_dt.argtypes = [cp, _DP, _DP]
+        L.or_compute_dt_box.argtypes = [cp, _DP, C.POINTER(C.c_int), C.POINTER(C.c_int), _DP]
+        L.or_face_states.argtypes = [cp, _DP, C.c_int, C.c_int, C.c_int, C.c_int, _DP, _DP]
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = C.c_int
         L.or_totals.argtypes = [cp, _DP, _DP]
         L.or_totals.restype = None
         L.or_enclosed_mass.argtypes = [cp, _DP, _DP]
@@ -150,6 +154,7 @@ class Oracle:
             c.ni_Q[i] = float(_opt(prob, "ni_Q", (0.0, 0.0))[i])
             c.ni_tau[i] = float(_opt(prob, "ni_tau", (1.0, 2.0))[i])
         c.ni_m = float(_opt(prob, "ni_m", 1.0))
+        c.centroid = 1 if _opt(prob, "centroid", False) else 0
         c.de_eps = float(getattr(prob, "de_eps", 1e-6)) if not isinstance(prob, dict) else float(prob.get("de_eps", 1e-6))
         self._mlp = None
         if mlp_weights is not None:
@@ -221,6 +226,31 @@ class Oracle:
         st = self._L.or_compute_dt(self._cfgp(), _ptr(U), C.byref(dt))
         if st == EINVAL:
             raise ValueError("oracle: invalid configuration")
+        return dt.value, st
+
+    def face_states(self, U: np.ndarray, i: int, j: int, k: int, d: int):
+        """Limited face primitives (lower, upper) of cell (i, j, k) along axis d, before the half step."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
+        wm = np.zeros(self.nvar)
+        wp = np.zeros(self.nvar)
+        st = self._L.or_face_states(self._cfgp(), _ptr(U), int(i), int(j), int(k), int(d), _ptr(wm), _ptr(wp))
+        if st == EINVAL:
+            raise ValueError("oracle: invalid cell, axis or configuration")
+        return wm, wp
+
+    def num_threads(self) -> int:
+        """Threads of the library's step (OpenMP team size; 1 for the serial build)."""
+        return int(self._L.or_num_threads())
+
+    def compute_dt_box(self, U: np.ndarray, lo, hi) -> tuple[float, int]:
+        """The CFL step over the cells of the box [lo, hi) (x, y, z order) only."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.shape())
+        dt = C.c_double(0.0)
+        lo3 = (C.c_int * 3)(*[int(v) for v in lo])
+        hi3 = (C.c_int * 3)(*[int(v) for v in hi])
+        st = self._L.or_compute_dt_box(self._cfgp(), _ptr(U), lo3, hi3, C.byref(dt))
+        if st == EINVAL:
+            raise ValueError("oracle: invalid box or configuration")
         return dt.value, st
 
     def totals(self, U: np.ndarray) -> np.ndarray:

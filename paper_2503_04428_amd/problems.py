@@ -63,6 +63,7 @@ class Problem:
     ni_Q: tuple = (0.0, 0.0)      # energy per decay of 56Ni and 56Co
     ni_tau: tuple = (1.0, 2.0)    # lifetimes of 56Ni and 56Co
     ni_m: float = 1.0             # mass of a 56Ni nucleus (56 m_u)
+    centroid: bool = False        # reconstruction about the volume centroids of spherical cells
 
     @property
     def nvar(self) -> int:

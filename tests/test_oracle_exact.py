@@ -94,3 +94,27 @@ def test_sedov_profile_center_behaviour():
         assert np.all(np.abs(U / np.array([1e-2, 0.05]) - 1.0 / g) < 1e-4)
         assert G[0] < 1e-8
         assert abs(P[0] - P[1]) < 1e-8 * P[0]
+
+
+def test_stored_exact_references_are_current():
+    """The exact references the benchmark reads (tests/golden, written by make_exact_references.py)
+    equal what the exact solvers give now, and the Sod file holds the textbook star state."""
+    import os
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sod = np.loadtxt(os.path.join(here, "sod1024_exact_t0.2.txt"))
+    faces = np.linspace(0.0, 1.0, 1025)
+    r, u, p = exact.cell_average(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, faces, 0.5, 0.2, g=1.4, sub=64)
+    assert np.array_equal(sod, np.stack([r, u, p], axis=1))
+    # cell 600 (x = 0.586) sits between the rarefaction tail and the contact: the left star state
+    assert sod[600, 0] == pytest.approx(0.42632, abs=1e-5)
+    assert sod[600, 1] == pytest.approx(0.92745, abs=1e-5)
+    assert sod[600, 2] == pytest.approx(0.30313, abs=1e-5)
+    xi0 = float(np.loadtxt(os.path.join(here, "sedov_xi0_gamma1.4.txt")))
+    assert xi0 == exact.sedov_xi0(1.4)
+    assert xi0 == pytest.approx(1.033, abs=0.002)
+    prof = np.loadtxt(os.path.join(here, "sedov_profile_gamma1.4.txt"))
+    sol = exact.sedov_profiles(1.4)
+    assert np.array_equal(prof[:, 1:], np.stack(sol.sol(prof[:, 0]), axis=1))
+    # strong-shock jump at lam = 1: G = (g+1)/(g-1), U = P = 2/(g+1)
+    assert prof[-1, 1:] == pytest.approx([6.0, 1.0 / 1.2, 1.0 / 1.2], rel=1e-12)
