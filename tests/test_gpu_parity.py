@@ -4,6 +4,7 @@ steps, on small grids spanning several workgroup tiles with ragged tails, every 
 limiter, Riemann solver, gravity mode, geometry and scalar count; and at full size on sampled
 cells of the first step."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -119,6 +120,34 @@ def test_fp64_parity_full_size_sedov_sampled(H):
         ob, st = o.step_box(U0, dt, lo, hi)
         gb = Ug[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
         assert_parity(gb, ob, what=f"sedov256 box {lo}-{hi}")
+
+
+def test_fp64_parity_full_size_sedov_200_steps(H):
+    """Sedov 256^3 in the benchmark's launch configuration, 200 steps (the workload's length) on
+    both sides, every cell compared at the FP64 bar after 100 and after 200 steps, and every time
+    step equal to the oracle's.  The oracle advances only the box around the blast (every other
+    cell keeps the ambient state exactly; pinned against whole-grid steps in the CPU tests)."""
+    from parity import BoxedRun
+    prob = P.sedov3d(n=256)
+    announce("fp64 full-size sedov 256^3, 200 steps, every cell")
+    lib = O.OMP_LIB_PATH if os.path.exists(O.OMP_LIB_PATH) else O.LIB_PATH
+    run = BoxedRun(O.Oracle(prob, library=lib), prob.U0.copy())
+    s = H.Solver(prob)
+    s.set_state(prob.U0)
+    for n in range(1, 201):
+        dt, st = run.compute_dt()
+        assert st == 0
+        assert s.compute_dt() == dt, f"step {n}"
+        assert run.step(dt) == 0
+        s.step(dt)
+        if n in (100, 200):
+            Ug = s.state_numpy()
+            assert_parity(Ug, run.U, what=f"sedov256 after {n} steps")
+            lo, hi = run.box
+            print(f"sedov 256^3 step {n}: blast box {lo}-{hi}, max relative difference "
+                  f"{max_rel(Ug, run.U):.3e}")
+            del Ug
+    s.close()
 
 
 def test_dt_and_totals_match_oracle(H):
