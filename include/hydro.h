@@ -209,6 +209,17 @@ hx_status hx_mlp_grad(const float *d_w, const float *d_x, const float *d_a, cons
                       long long n, float *d_grad, float *d_loss, void *d_work, size_t work_bytes,
                       void *hip_stream);
 
+/* hx_mlp_grad for callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same loss and gradient, bit for bit, with the block
+ * partials in a scratch array the library holds statically on every device it runs on (5.1 MB,
+ * 1024 partial rows, enough for any n since the gradient grid is capped at 1024 blocks; kept until
+ * the process ends).  No allocation, no workspace argument.  The array is shared by every call on a
+ * device and keeps the last call's partials (each call overwrites the rows it uses before reading
+ * them): calls that overlap on one device (different streams or threads) race.  HX_EINVAL for null
+ * pointers or n < 1, HX_ENOSPACE if n needs more partial rows than the array holds. */
+hx_status hx_mlp_grad_noalloc(const float *d_w, const float *d_x, const float *d_a, const float *d_t,
+                              const float *d_wt, long long n, float *d_grad, float *d_loss, void *hip_stream);
+
 /* One Adam update of the FP32 master weights d_w with moments d_m, d_v (step counts from 1). */
 hx_status hx_mlp_adam(float *d_w, const float *d_grad, float *d_m, float *d_v, int step, float lr, float beta1,
                       float beta2, float eps, void *hip_stream);

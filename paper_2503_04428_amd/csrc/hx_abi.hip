@@ -855,6 +855,19 @@ hx_status hx_mlp_grad(const float* d_w, const float* d_x, const float* d_a, cons
     return HX_OK;
 }
 
+hx_status hx_mlp_grad_noalloc(const float* d_w, const float* d_x, const float* d_a, const float* d_t,
+                              const float* d_wt, long long n, float* d_grad, float* d_loss, void* hip_stream)
+{
+    if (!d_w || !d_x || !d_a || !d_t || !d_wt || !d_grad || !d_loss || n < 1)
+        return fail(HX_EINVAL, "invalid argument");
+    const size_t need = hx_mlp_grad_workspace_bytes(n);
+    if (need > hx::mlp_grad_scratch_bytes())
+        return fail(HX_ENOSPACE, "%lld samples need %zu bytes of scratch, the static scratch holds %zu", n, need,
+                    hx::mlp_grad_scratch_bytes());
+    HIPCHECK(hx::launch_mlp_grad_noalloc(d_w, d_x, d_a, d_t, d_wt, n, d_grad, d_loss, (hipStream_t)hip_stream));
+    return HX_OK;
+}
+
 hx_status hx_mlp_adam(float* d_w, const float* d_grad, float* d_m, float* d_v, int step, float lr, float beta1,
                       float beta2, float eps, void* hip_stream)
 {

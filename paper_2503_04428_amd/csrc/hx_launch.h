@@ -76,6 +76,10 @@ hipError_t launch_mlp_features(const double* U, int nrows, int nf, int ratio, do
 int mlp_grad_blocks(long long n);
 hipError_t launch_mlp_grad(const float* w, const float* x, const float* a, const float* t, const float* wt,
                            long long n, float* grad, float* loss, float* part, hipStream_t s);
+// the same with the block partials in the library's static per-device scratch (no allocation)
+hipError_t launch_mlp_grad_noalloc(const float* w, const float* x, const float* a, const float* t, const float* wt,
+                                   long long n, float* grad, float* loss, hipStream_t s);
+size_t mlp_grad_scratch_bytes();
 hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v, int step, float lr, float b1, float b2,
                            float eps, hipStream_t s);
 

@@ -2,6 +2,8 @@
 // FP64 solutions, and the FP32 training kernels (forward + backward + Adam).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "hx_launch.h"
 #include "hx_mlp.h"
 
@@ -141,22 +143,23 @@ __device__ __forceinline__ float wave_sum_f(float v)
 }
 
 constexpr int GB = 256;  // threads per gradient block
+constexpr int GW = GB / 64;  // waves per gradient block
 
 // Per-sample FP32 forward/backward of L = sum wt (phi a - t)^2 (unnormalised); per-block sums of
-// the 1249 gradients, of the loss and of the weights go to part[block][1251].
+// the 1249 gradients, of the loss and of the weights go to part[block][1251].  Every wave adds its
+// wave sums into its own LDS row (one lane writes, so each row is summed in sample order), and the
+// rows are added in wave order at the end: the result does not depend on wave timing.
 __global__ void __launch_bounds__(GB) mlp_grad_kernel(const float* __restrict__ w, const float* __restrict__ x,
                                                       const float* __restrict__ a, const float* __restrict__ t,
                                                       const float* __restrict__ wt, long long n,
                                                       float* __restrict__ part)
 {
     __shared__ float sw[MLP_NPARAM];
-    __shared__ float sg[MLP_NPARAM + 2];
-    for (int i = threadIdx.x; i < MLP_NPARAM; i += GB) {
+    __shared__ float sg[GW][MLP_NPARAM + 2];
+    for (int i = threadIdx.x; i < MLP_NPARAM; i += GB)
         sw[i] = w[i];
-        sg[i] = 0.0f;
-    }
-    if (threadIdx.x < 2)
-        sg[MLP_NPARAM + threadIdx.x] = 0.0f;
+    for (int i = threadIdx.x; i < GW * (MLP_NPARAM + 2); i += GB)
+        sg[i / (MLP_NPARAM + 2)][i % (MLP_NPARAM + 2)] = 0.0f;
     __syncthreads();
     const float* W1 = sw + MLP_W1;
     const float* b1 = sw + MLP_B1;
@@ -165,6 +168,7 @@ __global__ void __launch_bounds__(GB) mlp_grad_kernel(const float* __restrict__ 
     const float* w3 = sw + MLP_W3;
     const float b3 = sw[MLP_B3];
     const bool lane0 = (threadIdx.x & 63) == 0;
+    float* row = sg[threadIdx.x >> 6];
 
     for (long long base = (long long)blockIdx.x * GB; base < n; base += (long long)gridDim.x * GB) {
         const long long e = base + threadIdx.x;
@@ -199,31 +203,31 @@ __global__ void __launch_bounds__(GB) mlp_grad_kernel(const float* __restrict__ 
         const float err = phi * ae - te;
         const float loss = we * err * err;
         const float dz = 2.0f * we * err * ae * phi * (1.0f - 0.5f * phi);
-        // reductions over the wave, one LDS atomic per parameter and wave
+        // wave sums, added by lane 0 into the wave's own row
         float r = wave_sum_f(loss);
         if (lane0)
-            atomicAdd(&sg[MLP_NPARAM], r);
+            row[MLP_NPARAM] += r;
         r = wave_sum_f(we);
         if (lane0)
-            atomicAdd(&sg[MLP_NPARAM + 1], r);
+            row[MLP_NPARAM + 1] += r;
         r = wave_sum_f(dz);
         if (lane0)
-            atomicAdd(&sg[MLP_B3], r);
+            row[MLP_B3] += r;
         float d2[32];
         for (int o = 0; o < 32; o++) {
             r = wave_sum_f(dz * h2[o]);
             if (lane0)
-                atomicAdd(&sg[MLP_W3 + o], r);
+                row[MLP_W3 + o] += r;
             d2[o] = dz * w3[o] * g2[o];
         }
         for (int o = 0; o < 32; o++) {
             r = wave_sum_f(d2[o]);
             if (lane0)
-                atomicAdd(&sg[MLP_B2 + o], r);
+                row[MLP_B2 + o] += r;
             for (int i = 0; i < 32; i++) {
                 r = wave_sum_f(d2[o] * h1[i]);
                 if (lane0)
-                    atomicAdd(&sg[MLP_W2 + o * 32 + i], r);
+                    row[MLP_W2 + o * 32 + i] += r;
             }
         }
         for (int i = 0; i < 32; i++) {
@@ -233,17 +237,21 @@ __global__ void __launch_bounds__(GB) mlp_grad_kernel(const float* __restrict__ 
             const float d1 = dh * g1[i];
             r = wave_sum_f(d1);
             if (lane0)
-                atomicAdd(&sg[MLP_B1 + i], r);
+                row[MLP_B1 + i] += r;
             for (int k = 0; k < 4; k++) {
                 r = wave_sum_f(d1 * xi[k]);
                 if (lane0)
-                    atomicAdd(&sg[MLP_W1 + i * 4 + k], r);
+                    row[MLP_W1 + i * 4 + k] += r;
             }
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < MLP_NPARAM + 2; i += GB)
-        part[(long long)blockIdx.x * (MLP_NPARAM + 2) + i] = sg[i];
+    for (int i = threadIdx.x; i < MLP_NPARAM + 2; i += GB) {
+        float s = sg[0][i];
+        for (int v = 1; v < GW; v++)
+            s += sg[v][i];
+        part[(long long)blockIdx.x * (MLP_NPARAM + 2) + i] = s;
+    }
 }
 
 // fixed-order sum of the block partials; grad = sum / sum(wt), loss = sum / sum(wt)
@@ -313,10 +321,12 @@ hipError_t launch_mlp_features(const double* U, int nrows, int nf, int ratio, do
     return hipGetLastError();
 }
 
+constexpr int MLP_GRAD_MAX_BLOCKS = 1024;  // largest grid of mlp_grad_kernel
+
 int mlp_grad_blocks(long long n)
 {
     long long nb = (n + GB - 1) / GB;
-    return (int)(nb > 1024 ? 1024 : (nb < 1 ? 1 : nb));
+    return (int)(nb > MLP_GRAD_MAX_BLOCKS ? MLP_GRAD_MAX_BLOCKS : (nb < 1 ? 1 : nb));
 }
 
 hipError_t launch_mlp_grad(const float* w, const float* x, const float* a, const float* t, const float* wt,
@@ -326,6 +336,51 @@ hipError_t launch_mlp_grad(const float* w, const float* x, const float* a, const
     mlp_grad_kernel<<<nb, GB, 0, s>>>(w, x, a, t, wt, n, part);
     mlp_grad_final_kernel<<<1, 256, 0, s>>>(part, nb, grad, loss);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free gradient entry point: the block partials of the largest grid
+// mlp_grad_kernel is launched with (1024 x 1251 floats, 5.1 MB).  Every device the library runs
+// on holds its own copy until the process ends; calls on one device share it.
+static __device__ __align__(256) float scratch[MLP_GRAD_MAX_BLOCKS * (MLP_NPARAM + 2)];
+
+constexpr int MLP_SCRATCH_MAX_DEVICES = 64;
+
+// Device address of this device's copy of the scratch array, looked up once per device (the
+// array's name in host code is only a stand-in for the symbol, not a device address).
+static hipError_t scratch_address(float** ptr)
+{
+    static std::mutex mu;
+    static float* addr[MLP_SCRATCH_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= MLP_SCRATCH_MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[dev] = static_cast<float*>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+size_t mlp_grad_scratch_bytes() { return sizeof(scratch); }
+
+hipError_t launch_mlp_grad_noalloc(const float* w, const float* x, const float* a, const float* t, const float* wt,
+                                   long long n, float* grad, float* loss, hipStream_t s)
+{
+    if (sizeof(float) * (size_t)mlp_grad_blocks(n) * (MLP_NPARAM + 2) > sizeof(scratch))
+        return hipErrorInvalidValue;  // cannot happen while the grid is capped at the array's rows
+    float* part = nullptr;
+    const hipError_t e = scratch_address(&part);
+    if (e != hipSuccess)
+        return e;
+    return launch_mlp_grad(w, x, a, t, wt, n, grad, loss, part, s);
 }
 
 hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v, int step, float lr, float b1, float b2,

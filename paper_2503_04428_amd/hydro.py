@@ -58,7 +58,8 @@ _lib = None
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
            "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
            "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_shift_grid", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
-           "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_adam", "hx_last_error", "hx_destroy"]
+           "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_grad_noalloc", "hx_mlp_adam", "hx_last_error",
+           "hx_destroy"]
 
 
 def load_library():
@@ -95,6 +96,7 @@ def load_library():
     L.hx_mlp_grad_workspace_bytes.argtypes = [C.c_longlong]
     L.hx_mlp_grad_workspace_bytes.restype = C.c_size_t
     L.hx_mlp_grad.argtypes = [vp, vp, vp, vp, vp, C.c_longlong, vp, vp, vp, C.c_size_t, vp]
+    L.hx_mlp_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_longlong, vp, vp, vp]
     L.hx_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.hx_last_error.argtypes = []
     L.hx_last_error.restype = C.c_char_p
@@ -388,6 +390,15 @@ class MlpTrainer:
             C.c_void_p(t.data_ptr()), C.c_void_p(wt.data_ptr()), C.c_longlong(n),
             C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.loss.data_ptr()),
             C.c_void_p(self.work.data_ptr()), C.c_size_t(self.work.numel()), _stream_ptr(self.torch, self.stream)))
+        return self.grad, self.loss
+
+    def gradient_noalloc(self, x, a, t, wt):
+        """gradient() through the allocation-free entry point (the library's static scratch)."""
+        n = x.shape[0]
+        _check(self.L, self.L.hx_mlp_grad_noalloc(
+            C.c_void_p(self.w.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(a.data_ptr()),
+            C.c_void_p(t.data_ptr()), C.c_void_p(wt.data_ptr()), C.c_longlong(n),
+            C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.loss.data_ptr()), _stream_ptr(self.torch, self.stream)))
         return self.grad, self.loss
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
