@@ -104,6 +104,15 @@ typedef struct {
     double ni_Q[2];         /* energy released per decay of 56Ni and of 56Co, >= 0 */
     double ni_tau[2];       /* lifetimes of 56Ni and 56Co, 0 < tau_Ni < tau_Co */
     double ni_m;            /* mass of one 56Ni nucleus (56 m_u in the caller's units), > 0 */
+    int centroid;           /* 1: reconstruct about the volume centroids of spherical cells (Sect.
+                               3.1.1: non-uniform radial and angular spacing) instead of the face
+                               midpoints: along r (measure r^2 dr) and theta (sin theta dtheta) the
+                               slopes use the distances between centroids, the face values are
+                               x_c + (x_+ - x_c) sigma and x_c - (x_c - x_-) sigma, and the increment
+                               is bounded so that both stay between the neighbouring cell values;
+                               a ghost cell's centroid is its image's, mirrored or translated like
+                               its faces.  Cartesian grids and phi are unchanged.  Not with the
+                               learned limiter.  0: face midpoints */
 } hx_config;
 
 /* Device bytes the caller must provide to hx_create for this configuration, or 0 if the

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -70,7 +71,7 @@ int bc_map(int i, int n, int lo, int hi, bool& flip)
 
 struct Layout {
     size_t state[2];
-    size_t tab[3][3];  // cm, cp, w per axis
+    size_t tab[3][4];  // cm, cp, w, kap per axis
     size_t rabs, sabs, rf, vr, hr, ct, sf;
     size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp, time, xfaces;
     size_t total;
@@ -145,6 +146,10 @@ hx_status validate(const hx_config* c)
             !std::isfinite(c->ni_Q[0]) || !std::isfinite(c->ni_Q[1]))
             return fail(HX_EINVAL, "the 56Ni heating needs ni_m > 0 and finite Q >= 0");
     }
+    if (c->centroid != 0 && c->centroid != 1)
+        return fail(HX_EINVAL, "centroid must be 0 or 1 (got %d)", c->centroid);
+    if (c->centroid && c->limiter == HX_LIMITER_MLP)
+        return fail(HX_EINVAL, "reconstruction about volume centroids is not built with the learned limiter");
     if (c->precision != HX_PRECISION_FP64 && c->precision != HX_PRECISION_FP32)
         return fail(HX_EINVAL, "unknown precision %d", c->precision);
     if (!(c->gamma > 1.0) || !(c->cfl > 0.0))
@@ -208,7 +213,7 @@ Layout layout(const hx_config* c)
     L.state[1] = take(rb * nv * nc);
     for (int d = 0; d < 3; d++) {
         L.ntab[d] = d < c->ndim ? c->n[d] + 2 * c->nghost : 1;
-        for (int t = 0; t < 3; t++)
+        for (int t = 0; t < 4; t++)
             L.tab[d][t] = take(sizeof(double) * L.ntab[d]);
     }
     L.rabs = take(sizeof(double) * L.ntab[0]);
@@ -289,24 +294,53 @@ void build_geometry(hx_ctx* x, std::vector<double>& h, std::vector<std::pair<siz
         spans.push_back({off, h.size()});
         h.insert(h.end(), v.begin(), v.end());
     };
+    // reconstruction position of cell i on axis d: the face midpoint, or with the centroid option
+    // the volume centroid of a spherical cell along r (measure r^2 dr) and theta (sin theta dtheta);
+    // a ghost cell's is its image's, mirrored about the boundary face or moved across a periodic axis
+    const bool cen = c.centroid && c.geom == HX_GEOM_SPH;
+    std::function<double(int, int)> xrec = [&](int d, int i) -> double {
+        if (!cen || d == 2)
+            return xcen(d, i);
+        const int n = c.n[d];
+        if (i < 0)
+            return c.bc[d][0] == HX_BOUNDARY_PERIODIC ? xrec(d, i + n) - (xf(d, n) - xf(d, 0))
+                                                      : 2.0 * xf(d, 0) - xrec(d, -1 - i);
+        if (i >= n)
+            return c.bc[d][1] == HX_BOUNDARY_PERIODIC ? xrec(d, i - n) + (xf(d, n) - xf(d, 0))
+                                                      : 2.0 * xf(d, n) - xrec(d, 2 * n - 1 - i);
+        const double a = xf(d, i), b = xf(d, i + 1);
+        if (d == 0)
+            return 0.75 * ((b + a) * (b * b + a * a)) / (b * b + b * a + a * a);
+        return ((std::sin(b) - b * std::cos(b)) - (std::sin(a) - a * std::cos(a))) / (std::cos(a) - std::cos(b));
+    };
     for (int d = 0; d < 3; d++) {
         const bool act = d < c.ndim;
         const int nt = x->L.ntab[d];
-        std::vector<double> cm(nt, 0.5), cp(nt, 0.5), w(nt, 0.0);
+        std::vector<double> cm(nt, 0.5), cp(nt, 0.5), w(nt, 0.0), kap(nt, 1.0);
         for (int t = 0; t < nt; t++) {
             const int i = act ? t - ng : 0;
             bool fl;
             const int im = act ? bc_map(i, c.n[d], c.bc[d][0], c.bc[d][1], fl) : 0;
             w[t] = dxc(d, im);
             if (act && i - 1 >= -ng && i + 1 <= c.n[d] + ng - 1) {
-                const double half = 0.5 * dxc(d, i);
-                cm[t] = half / (xcen(d, i) - xcen(d, i - 1));
-                cp[t] = half / (xcen(d, i + 1) - xcen(d, i));
+                if (cen && d < 2) {
+                    // increments (x_+ - x_c) sigma and (x_c - x_-) sigma about the centroid x_c
+                    const double xc = xrec(d, i);
+                    const double hp = xf(d, i + 1) - xc;
+                    cm[t] = hp / (xc - xrec(d, i - 1));
+                    cp[t] = hp / (xrec(d, i + 1) - xc);
+                    kap[t] = (xc - xf(d, i)) / hp;
+                } else {
+                    const double half = 0.5 * dxc(d, i);
+                    cm[t] = half / (xcen(d, i) - xcen(d, i - 1));
+                    cp[t] = half / (xcen(d, i + 1) - xcen(d, i));
+                }
             }
         }
         push(x->L.tab[d][0], cm);
         push(x->L.tab[d][1], cp);
         push(x->L.tab[d][2], w);
+        push(x->L.tab[d][3], kap);
     }
     {
         const int nt = x->L.ntab[0];
@@ -409,6 +443,7 @@ hx::Geo geo_of(hx_ctx* x)
         g.cm[d] = at<double>(x, x->L.tab[d][0]);
         g.cp[d] = at<double>(x, x->L.tab[d][1]);
         g.w[d] = at<double>(x, x->L.tab[d][2]);
+        g.kap[d] = at<double>(x, x->L.tab[d][3]);
     }
     g.rabs = at<double>(x, x->L.rabs);
     g.sabs = at<double>(x, x->L.sabs);
@@ -495,8 +530,10 @@ hx_status enqueue_step(hx_ctx* x, double dt, const double* d_dt)
     }
     p.ni_m = c.ni_m;
     p.t_in = at<double>(x, x->L.time);
-    // the fixed HLLC + van Leer sweeps are built without the 56Ni heating
-    const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC && !c.ni_heating;
+    p.centroid = c.centroid && c.geom == HX_GEOM_SPH ? 1 : 0;
+    // the fixed HLLC + van Leer sweeps are built without the 56Ni heating and with face-midpoint
+    // reconstruction
+    const bool spec = c.limiter == HX_LIMITER_VANLEER && c.riemann == HX_RIEMANN_HLLC && !c.ni_heating && !p.centroid;
     if (c.limiter == HX_LIMITER_MLP && !x->have_mlp)
         return fail(HX_ESTATE, "the learned limiter needs hx_set_mlp before stepping");
     // the instantiation for this configuration; with occ, only its workgroups per compute unit

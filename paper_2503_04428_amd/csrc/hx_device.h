@@ -234,6 +234,30 @@ __device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w, R* T = n
     return PrimImpl<R, NV, DE, EOS>::run(g, q, w, T);
 }
 
+// CFL signal rate of the FP32 form, sum_d (|u_d| + c_s) rw_d with rw_d the reciprocal widths rounded
+// once to FP32: the internal energy E - |m|^2/(2 rho) is recovered in FP64 (to_prim), the rest is
+// FP32; the maximum over cells and the time step cfl / max stay FP64.  A negative value marks a
+// non-physical state.  The sweep's store and the standalone CFL kernel both use it, so the time
+// step of a state does not depend on which of them computed it.
+template <int NV, int NDIM>
+__device__ __forceinline__ double cfl_rate_f32(const float* q, const Gas<float>& g, const float* rw)
+{
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+        fin = fin && isfinite(q[v]);
+    float w[NV];
+    const float inv = to_prim<float, NV>(g, q, w);
+    if (!fin || !(q[0] > 0.0f) || !(w[4] > 0.0f))
+        return -1.0;
+    const float cs = __builtin_amdgcn_sqrtf(g.gamma * w[4] * inv);
+    float s = 0.0f;
+#pragma unroll
+    for (int d = 0; d < NDIM; d++)
+        s += (fabsf(w[1 + d]) + cs) * rw[d];
+    return (double)s;
+}
+
 // gas + radiation EoS: primitives of two conserved states (the faces of one Riemann problem) with
 // their two temperature solves in one loop; the same values as two calls of to_prim
 template <int NV, bool DE = false>

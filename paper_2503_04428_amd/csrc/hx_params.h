@@ -23,7 +23,10 @@ namespace hx {
 
 // Per-axis geometry tables (FP64, device), all indexed by cell index + ng on active axes
 // (ghost cells included), by 0 on inactive axes:
-//   cm, cp : half-width over the left / right centre distance (half increments of a slope)
+//   cm, cp : the upper face's extrapolation distance over the left / right centre distance (scaled
+//            one-sided differences: the limited upper face increment is limiter(cm dm, cp dp))
+//   kap    : the lower face's extrapolation distance over the upper one (1 with face-midpoint
+//            centres; with volume centroids (x_c - x_-) / (x_+ - x_c))
 //   w      : coordinate width of the cell's image (dx; dr, dtheta, dphi)
 // Spherical extras, indexed the same way:
 //   rabs   : |r_c| of the image cell (axis 0),  sabs : |sin theta_c| of the image cell (axis 1)
@@ -33,6 +36,7 @@ namespace hx {
 struct Geo {
     const double* cm[3];
     const double* cp[3];
+    const double* kap[3];
     const double* w[3];
     const double* rabs;
     const double* sabs;
@@ -71,6 +75,7 @@ struct SweepParams {
     double ni_tau[2];    // lifetimes of 56Ni and 56Co
     double ni_m;         // mass of a 56Ni nucleus
     const double* t_in;  // the decay clock at the start of the step (advanced after the sweep)
+    int centroid;        // 1: reconstruction about the volume centroids of spherical cells
 };
 
 }  // namespace hx

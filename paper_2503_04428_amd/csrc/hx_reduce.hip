@@ -41,6 +41,44 @@ __global__ void __launch_bounds__(RB) dt_partial_kernel(const DtParams p)
         const long long r = c / p.n[0];
         const int j = (int)(r % p.n[1]);
         const int k = (int)(r / p.n[1]);
+        if constexpr (sizeof(R) == 4) {
+            // the FP32 form's rate, as the sweep forms it when it stores a cell
+            if (p.eos == 0) {
+                float qf[5];
+                bool fin = true;
+#pragma unroll
+                for (int v = 0; v < 5; v++)
+                    qf[v] = (float)U[(long long)v * ncell + c];
+                for (int v = 5; v < p.nvar; v++)
+                    fin = fin && isfinite((double)U[(long long)v * ncell + c]);
+                Gas<float> g;
+                g.gamma = (float)p.gamma;
+                g.gm1 = (float)p.gm1;
+                g.inv_gm1 = (float)(1.0 / p.gm1);
+                float rw[3] = {0.0f, 0.0f, 0.0f};
+                for (int d = 0; d < p.ndim; d++) {
+                    double w;
+                    if (p.geom == HX_CART) {
+                        const int id = d == 0 ? i : (d == 1 ? j : k);
+                        w = p.geo.w[d][id + p.ng];
+                    } else if (d == 0) {
+                        w = p.geo.w[0][i + p.ng];
+                    } else if (d == 1) {
+                        w = p.geo.rabs[i + p.ng] * p.geo.w[1][j + p.ng];
+                    } else {
+                        w = p.geo.rabs[i + p.ng] * p.geo.sabs[j + p.ng] * p.geo.w[2][k + p.ng];
+                    }
+                    rw[d] = (float)(1.0 / w);
+                }
+                const double s = cfl_rate_f32<5, 3>(qf, g, rw);
+                if (!fin || s < 0.0) {
+                    bad = 1;
+                    continue;
+                }
+                smax = fmax(smax, s);
+                continue;
+            }
+        }
         double q[5];
 #pragma unroll
         for (int v = 0; v < 5; v++)

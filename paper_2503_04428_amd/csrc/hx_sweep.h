@@ -63,6 +63,17 @@ struct MinWaves {
     static constexpr int value = sizeof(R) == 8 ? fp64 : fp32;
 };
 
+// Two-plane load prefetch: the 3D FP64 sweeps that run one wave per SIMD (their idle issue slots
+// are mostly waits on the plane loads); HX_PREFETCH2 = 0 turns it off, 1 forces it everywhere.
+template <typename R, int NV, int NDIM, int GEOM, int SPEC>
+struct PrefetchTwo {
+#ifdef HX_PREFETCH2
+    static constexpr bool value = HX_PREFETCH2 != 0;
+#else
+    static constexpr bool value = sizeof(R) == 8 && MinWaves<R, NV, NDIM, GEOM, SPEC>::value == 1;
+#endif
+};
+
 template <int NDIM>
 struct Tile;
 template <>
@@ -126,7 +137,7 @@ __device__ __forceinline__ R from_right(R v)
 
 // CFL signal rate sum_d (|u_d| + c_s)/dx_d of a conserved state, in FP64, in the operation order
 // of the reference definition (EOS = 1: P and c_s of the gas + radiation EoS); returns a negative
-// value for a non-physical state
+// value for a non-physical state.  The FP32 form takes cfl_rate_f32 (hx_device.h) instead.
 template <typename R, int NV, int NDIM, int EOS = 0>
 __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const double* wd, const Gas<R>& eg)
 {
@@ -190,6 +201,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     constexpr int NYB = NDIM >= 2 ? NT : 1;
     constexpr int TX = BX - 2;
     constexpr int TY = NDIM >= 2 ? BY - 2 : 1;
+    // 3D sweeps with one wave per SIMD issue the loads of a plane two iterations before its use
+    // (nothing else hides their latency); the others one iteration before
+    constexpr bool PF2 = NDIM == 3 && PrefetchTwo<R, NV, NDIM, GEOM, SPEC>::value;
+    // reconstruction about volume centroids (spherical r and theta) in the run-time variants
+    constexpr bool CEN = GEOM == HX_SPH && (SPEC == 0 || SPEC == 3 || SPEC == 4 || SPEC == 5);
 
     __shared__ R sW[NSLOT][NV][RY * RX];  // primitives of a plane incl. a 2-cell ring
     __shared__ R sFy[NV][NYB];            // +y half-step state of every predictor cell
@@ -278,6 +294,15 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         cmy = N::from_d(p.geo.cm[1][gy]);
         cpy = N::from_d(p.geo.cp[1][gy]);
     }
+    // lower-face over upper-face extrapolation distance of x and y (1 about face midpoints, and
+    // always along z); the bound on the increments applies with volume centroids only
+    const bool cen = CEN && p.centroid != 0;
+    R kpx = R(1), kpy = R(1);
+    if constexpr (CEN) {
+        kpx = N::from_d(p.geo.kap[0][gx]);
+        if (NDIM >= 2)
+            kpy = N::from_d(p.geo.kap[1][gy]);
+    }
     // predictor coefficients dt / (2 width) for x and y (widths of the image cell)
     R lamx, lamy = R(0);
     double wx = p.geo.w[0][gx], wy = 0.0;
@@ -294,6 +319,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             lamy = N::from_d(dtd / (2.0 * wy));
         }
     }
+    // FP32 form: reciprocal widths of the CFL rate, rounded once to FP32 (x and y per column)
+    const float rwx = sizeof(R) == 4 ? (float)(1.0 / wx) : 0.0f;
+    const float rwy = sizeof(R) == 4 && NDIM >= 2 ? (float)(1.0 / wy) : 0.0f;
     // gravity of this column's image (z flips handled per plane)
     double gcol[3] = {0.0, 0.0, 0.0};
     if (p.gravity == HX_GRAV_UNIFORM) {
@@ -303,6 +331,36 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     } else if (p.gravity != HX_GRAV_NONE) {
         gcol[0] = fx ? -p.gr[ii] : p.gr[ii];
     }
+
+    // spherical per-column geometry used in every plane: held in registers by the two-plane
+    // prefetch sweeps (for the reason above), read where used by the others
+    struct SphCol {
+        double rsxy, vrct, hrw, rm, rp, ctj, hrsm, hrsp, smm, spp, dph2;
+    } sc = {};
+    if constexpr (GEOM == HX_SPH && PF2) {
+        sc.rsxy = p.geo.rabs[gx] * p.geo.sabs[gy];
+        sc.vrct = p.geo.vr[ii] * p.geo.ct[jj];
+        sc.hrw = p.geo.hr[ii] * p.geo.w[1][jj + ng];
+        sc.rm = p.geo.rf[ii];
+        sc.rp = p.geo.rf[ii + 1];
+        sc.ctj = p.geo.ct[jj];
+        sc.hrsm = p.geo.hr[ii] * p.geo.sf[jj];
+        sc.hrsp = p.geo.hr[ii] * p.geo.sf[jj + 1];
+        sc.smm = p.geo.sf[jj];
+        sc.spp = p.geo.sf[jj + 1];
+        sc.dph2 = p.geo.w[2][0];
+    }
+    auto g_rsxy = [&]() { return PF2 ? sc.rsxy : p.geo.rabs[gx] * p.geo.sabs[gy]; };
+    auto g_vrct = [&]() { return PF2 ? sc.vrct : p.geo.vr[ii] * p.geo.ct[jj]; };
+    auto g_hrw = [&]() { return PF2 ? sc.hrw : p.geo.hr[ii] * p.geo.w[1][jj + ng]; };
+    auto g_rm = [&]() { return PF2 ? sc.rm : p.geo.rf[ii]; };
+    auto g_rp = [&]() { return PF2 ? sc.rp : p.geo.rf[ii + 1]; };
+    auto g_ctj = [&]() { return PF2 ? sc.ctj : p.geo.ct[jj]; };
+    auto g_hrsm = [&]() { return PF2 ? sc.hrsm : p.geo.hr[ii] * p.geo.sf[jj]; };
+    auto g_hrsp = [&]() { return PF2 ? sc.hrsp : p.geo.hr[ii] * p.geo.sf[jj + 1]; };
+    auto g_smm = [&]() { return PF2 ? sc.smm : p.geo.sf[jj]; };
+    auto g_spp = [&]() { return PF2 ? sc.spp : p.geo.sf[jj + 1]; };
+    auto g_dph2 = [&]() { return PF2 ? sc.dph2 : p.geo.w[2][0]; };
 
     // ------------------------------------------------------------------ plane loader
     // The primitives of the (RX x RY) rectangle of a plane (predictor cells plus an S-wide ring)
@@ -413,7 +471,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         mlp_fill_shared(p.mlp, tid, NT, sMlp);
     // limited half increments of one axis; st(j, v) = primitive v at offset j - 2 along the axis
     // (all stencil values are read before the first limiter branch, so that their loads overlap)
-    auto slopes = [&](auto&& st, R cm, R cp, R* dl) {
+    auto slopes = [&](auto&& st, R cm, R cp, R kp, R* dl) {
         R a[NV], b[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
@@ -424,23 +482,52 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
         for (int v = 0; v < NV; v++)
             dl[v] = limit<R>(lim, a[v], b[v]);
+        // about volume centroids an extrapolation distance can exceed half the distance to the
+        // neighbouring centroid: the increment is bounded so that both face values stay between
+        // the neighbouring cell values, |dl| <= |w+ - w| and kp |dl| <= |w - w-|
+        if constexpr (CEN) {
+            if (cen) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    if (dl[v] != R(0)) {
+                        const R dm = st(2, v) - st(1, v), dp = st(3, v) - st(2, v);
+                        const R bound = fmin(N::abs_(dp), N::div(N::abs_(dm), kp));
+                        if (N::abs_(dl[v]) > bound)
+                            dl[v] = dl[v] > R(0) ? bound : -bound;
+                    }
+                }
+            }
+        }
     };
     // learned form of slopes() for the axes a0 .. a0+na-1 (na <= 2); st(a, j, v) = primitive v at
     // offset j - 2 along axis a.  The stencils are read again after the queue fence, so that they
     // are not held in registers across the network tiles.
     auto slopes_mlp = [&](auto&& st, int a0, int na, const R* cmv, const R* cpv, R (*dl)[NV]) {
         const int lane = tid & 63, wv = tid >> 6;
-        float d[2][NV][4];  // stencil differences
         unsigned long long bal[2][NV];  // candidates: monotone stencils, d1 d2 > 0
+        unsigned first[2][NV];          // queue slot of the first candidate of (axis, variable)
         unsigned total = 0;
+        // one (axis, variable) at a time: its four differences are queued (d / max|d| as BF16)
+        // by the candidate lanes and are dead before the next stencil is read
 #pragma unroll
         for (int a = 0; a < na; a++)
 #pragma unroll
             for (int v = 0; v < NV; v++) {
+                float dd[4];
 #pragma unroll
                 for (int j = 0; j < 4; j++)
-                    d[a][v][j] = st(a0 + a, j + 1, v) - st(a0 + a, j, v);
-                bal[a][v] = __builtin_amdgcn_ballot_w64(d[a][v][1] * d[a][v][2] > 0.0f);
+                    dd[j] = st(a0 + a, j + 1, v) - st(a0 + a, j, v);
+                bal[a][v] = __builtin_amdgcn_ballot_w64(dd[1] * dd[2] > 0.0f);
+                first[a][v] = total;
+                if (bal[a][v]) {
+                    const float is = __builtin_amdgcn_rcpf(
+                        fmaxf(fmaxf(fabsf(dd[0]), fabsf(dd[1])), fmaxf(fabsf(dd[2]), fabsf(dd[3]))));
+                    const unsigned long long x = __builtin_bit_cast(
+                        unsigned long long, pack_x(dd[0] * is, dd[1] * is, dd[2] * is, dd[3] * is));
+                    if ((bal[a][v] >> lane) & 1ull)
+                        sQ[wv][total + __builtin_amdgcn_mbcnt_hi((unsigned)(bal[a][v] >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)bal[a][v], 0u))] = x;
+                }
                 total += (unsigned)__builtin_popcountll(bal[a][v]);
                 dl[a][v] = R(0);
             }
@@ -448,30 +535,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             return;
         auto cand = [&](int a, int v) { return ((bal[a][v] >> lane) & 1ull) != 0; };
         auto slot = [&](int a, int v) {
-            unsigned base = 0;
-#pragma unroll
-            for (int b = 0; b <= a; b++)
-#pragma unroll
-                for (int u = 0; u < NV; u++)
-                    if (b < a || u < v)
-                        base += (unsigned)__builtin_popcountll(bal[b][u]);
-            return (int)(base + __builtin_amdgcn_mbcnt_hi((unsigned)(bal[a][v] >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((unsigned)bal[a][v], 0u)));
+            return (int)(first[a][v] + __builtin_amdgcn_mbcnt_hi((unsigned)(bal[a][v] >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)bal[a][v], 0u)));
         };
-        // queue d / max|d| of every candidate as BF16 (stencils without candidates skip, uniformly)
-#pragma unroll
-        for (int a = 0; a < na; a++)
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                if (bal[a][v]) {
-                    const float* dd = d[a][v];
-                    const float is = __builtin_amdgcn_rcpf(
-                        fmaxf(fmaxf(fabsf(dd[0]), fabsf(dd[1])), fmaxf(fabsf(dd[2]), fabsf(dd[3]))));
-                    const unsigned long long x = __builtin_bit_cast(
-                        unsigned long long, pack_x(dd[0] * is, dd[1] * is, dd[2] * is, dd[3] * is));
-                    if (cand(a, v))
-                        sQ[wv][slot(a, v)] = x;
-                }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -513,6 +579,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     // ------------------------------------------------------------------ persistent state
     // own column: wz[S + j] = primitives of plane k + j (j = -S..S), qz[j] = conserved of plane k + j
     R wz[2 * S + 1][NV], qz[S + 1][NV];
+    R qpf[PF2 ? NV : 1], rpf[PF2 ? NV : 1];  // two-plane prefetch: own column and ring cell in flight
+    // z geometry (cm, cp, width) of the next plane, loaded one iteration ahead by the two-plane
+    // prefetch sweeps: a load issued after the plane loads would make its wait (the memory
+    // counter is in order) a wait for the plane loads too
+    double zgn[3] = {0.0, 0.0, 0.0};
     R acc[NV];     // plane k-1: U^n + x and y flux terms
     R fzlo[NV];    // z flux through the lower face of plane k-1
     R uzp[NV];     // +z half-step state of plane k-1
@@ -570,6 +641,16 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
         for (int v = 0; v < NV; v++)
             uzp[v] = qz[0][v];
+        // two-plane prefetch: the loads the first iteration commits, after the z geometry of its
+        // plane
+        if constexpr (PF2) {
+            const int gz0 = clamp_ghost(kbeg, n2, ng) + ng;
+            zgn[0] = p.geo.cm[2][gz0];
+            zgn[1] = p.geo.cp[2][gz0];
+            zgn[2] = p.geo.w[2][gz0];
+            issue_own(kbeg + S, qpf);
+            issue_ring(kbeg + 1, rpf);
+        }
     } else {
         R qr[NV];
         issue_own(0, qz[0]);
@@ -583,27 +664,52 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     for (int k = kbeg; k <= kend; ++k) {
         const int slot = NDIM == 3 ? (k & 1) : 0;
         R qring[NV];
+        // z geometry of plane k: cm, cp, width
+        double zg[3] = {0.0, 0.0, 0.0};
         if (NDIM == 3) {
-            issue_own(k + S, qz[S]);
-            issue_ring(k + 1, qring);
+            const int gzk = clamp_ghost(k, n2, ng) + ng;
+            if constexpr (PF2) {
+                // the loads of plane k+1 (own column k+S) and this plane's geometry were issued
+                // one iteration ago; the next plane's geometry, then the loads of the next planes
+                // go out now and have a whole iteration to arrive
+#pragma unroll
+                for (int t = 0; t < 3; t++)
+                    zg[t] = zgn[t];
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    qz[S][v] = qpf[v];
+                    qring[v] = rpf[v];
+                }
+                const int gzn = clamp_ghost(k + 1, n2, ng) + ng;
+                zgn[0] = p.geo.cm[2][gzn];
+                zgn[1] = p.geo.cp[2][gzn];
+                zgn[2] = p.geo.w[2][gzn];
+                issue_own(k + S + 1, qpf);
+                issue_ring(k + 2, rpf);
+            } else {
+                // geometry first: its wait then does not include the plane loads
+                zg[0] = p.geo.cm[2][gzk];
+                zg[1] = p.geo.cp[2][gzk];
+                zg[2] = p.geo.w[2][gzk];
+                issue_own(k + S, qz[S]);
+                issue_ring(k + 1, qring);
+            }
         }
         R(&wcur)[NV] = wz[S];
         R(&qcur)[NV] = qz[0];
 
         // -------------------------------------------------------------- predictor, plane k
         bool fzk = false;
-        int gz = 0;
         double w2k = 0.0;  // z width of plane k
         R cmz = R(0), cpz = R(0), lamz = R(0);
         double g[3] = {gcol[0], gcol[1], gcol[2]};
         if (NDIM == 3) {
             const int kc = clamp_ghost(k, n2, ng);
             bc_image(kc, n2, ng, p.bc[2][0], p.bc[2][1], fzk);  // sets the z-mirror flag
-            gz = kc + ng;
-            cmz = N::from_d(p.geo.cm[2][gz]);
-            cpz = N::from_d(p.geo.cp[2][gz]);
-            w2k = p.geo.w[2][gz];
-            double wz = GEOM == HX_CART ? w2k : p.geo.rabs[gx] * p.geo.sabs[gy] * w2k;
+            cmz = N::from_d(zg[0]);
+            cpz = N::from_d(zg[1]);
+            w2k = zg[2];
+            double wz = GEOM == HX_CART ? w2k : g_rsxy() * w2k;
             lamz = N::from_d(dtd / (2.0 * wz));
             if (fzk && p.gravity == HX_GRAV_UNIFORM)
                 g[2] = -g[2];
@@ -620,8 +726,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         // holding 3 NV of them across the predictor (the register budget of two waves per SIMD)
         constexpr bool RESLOPE = !MLP && sizeof(R) == 8 && HX_RESLOPE_FP64;
         R cm3[3] = {cmx, cmy, cmz}, cp3[3] = {cpx, cpy, cpz};
+        const R kp3[3] = {kpx, kpy, R(1)};
         auto slope_of = [&](int d, R* dl) {
-            slopes([&](int j, int v) { return stv(d, j, v); }, cm3[d], cp3[d], dl);
+            slopes([&](int j, int v) { return stv(d, j, v); }, cm3[d], cp3[d], kp3[d], dl);
         };
         // inputs of slope_of made opaque, so that it is evaluated again rather than kept
         auto reslope_fence = [&]() {
@@ -669,15 +776,24 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         {
             // x
             if constexpr (MLP) {
+                // the learned form evaluates the network for every axis here, where the least
+                // state is live (no half-step increments, no face states): x and y, then, after
+                // the commit of the next planes that its five-plane z stencil needs, z
                 const R cmv[2] = {cmx, cmy}, cpv[2] = {cpx, cpy};
                 slopes_mlp(stv, 0, NDIM >= 2 ? 2 : 1, cmv, cpv, dlt);
+                if constexpr (NDIM == 3) {
+                    commit_own(k + S, qz[S], wz[2 * S]);
+                    commit_ring(k + 1, (k + 1) & 1, qring);
+                    store_own((k + 1) & 1, wz[S + 1]);
+                    slopes_mlp(stv, 2, 1, &cmz, &cpz, dlt + 2);
+                }
             } else {
-                slopes([&](int j, int v) { return stv(0, j, v); }, cmx, cpx, dlt[0]);
+                slopes([&](int j, int v) { return stv(0, j, v); }, cmx, cpx, kpx, dlt[0]);
             }
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                wm[v] = wcur[v] - dlt[0][v];
+                wm[v] = wcur[v] - kpx * dlt[0][v];
                 wp[v] = wcur[v] + dlt[0][v];
             }
             pred_cons(0, wm, wp, um, up);
@@ -692,11 +808,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         }
         if (NDIM >= 2) {
             if constexpr (!MLP)
-                slopes([&](int j, int v) { return stv(1, j, v); }, cmy, cpy, dlt[1]);
+                slopes([&](int j, int v) { return stv(1, j, v); }, cmy, cpy, kpy, dlt[1]);
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                wm[v] = wcur[v] - dlt[1][v];
+                wm[v] = wcur[v] - kpy * dlt[1][v];
                 wp[v] = wcur[v] + dlt[1][v];
             }
             pred_cons(1, wm, wp, um, up);
@@ -710,13 +826,12 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 du[NV - 1] += lamy * (pe_n() * (wm[1 + 1] - wp[1 + 1]));
         }
         if (NDIM == 3) {
-            commit_own(k + S, qz[S], wz[2 * S]);
-            commit_ring(k + 1, (k + 1) & 1, qring);
-            store_own((k + 1) & 1, wz[S + 1]);
-            if constexpr (MLP)
-                slopes_mlp(stv, 2, 1, &cmz, &cpz, dlt + 2);
-            else
-                slopes([&](int j, int v) { return stv(2, j, v); }, cmz, cpz, dlt[2]);
+            if constexpr (!MLP) {
+                commit_own(k + S, qz[S], wz[2 * S]);
+                commit_ring(k + 1, (k + 1) & 1, qring);
+                store_own((k + 1) & 1, wz[S + 1]);
+                slopes([&](int j, int v) { return stv(2, j, v); }, cmz, cpz, R(1), dlt[2]);
+            }
             R wm[NV], wp[NV], um[NV], up[NV], fm[NV], fp[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
@@ -776,7 +891,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 R ws[NV], qs[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
+                    ws[v] = side ? wcur[v] + dd[v] : wcur[v] - kp3[d] * dd[v];
                 if constexpr (EOS == 1)
                     to_cons_e<NV, DE>(ws, ef[d][side], qs);
                 else
@@ -838,7 +953,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const R dv = RESLOPE && bad ? R(0) : dd[v];
-                    ws[v] = side ? wcur[v] + dv : wcur[v] - dv;
+                    ws[v] = side ? wcur[v] + dv : wcur[v] - kp3[d] * dv;
                 }
                 face_cons(d, side, bad, ws, out);
                 if (!bad) {
@@ -850,7 +965,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             }
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                ws[v] = side ? wcur[v] + dd[v] : wcur[v] - dd[v];
+                ws[v] = side ? wcur[v] + dd[v] : wcur[v] - kp3[d] * dd[v];
             face_cons(d, side, false, ws, out);
 #pragma unroll
             for (int v = 0; v < NV; v++)
@@ -929,9 +1044,9 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                         acc[NV - 1] += mu * (pe_prev * (ufzlo - ufz));
                 } else {
                     const double dph = w2prev;
-                    const double dV = p.geo.vr[ii] * p.geo.ct[jj] * dph;
+                    const double dV = g_vrct() * dph;
                     const R kv = N::from_d(dtd / dV);
-                    const R dS = N::from_d(p.geo.hr[ii] * p.geo.w[1][jj + ng]);
+                    const R dS = N::from_d(g_hrw());
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += kv * (fzlo[v] * dS - Fz[v] * dS);
@@ -959,8 +1074,14 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     Un[(long long)v * p.plane + off] = acc[v];
-                double wd[3] = {wx, wy, GEOM == HX_CART ? w2prev : p.geo.rabs[gx] * p.geo.sabs[gy] * w2prev};
-                const double sr = cfl_rate<R, NV, NDIM, EOS>(acc, p.gamma, wd, gas);
+                double sr;
+                if constexpr (sizeof(R) == 4) {
+                    const float rw[3] = {rwx, rwy, (float)(1.0 / (GEOM == HX_CART ? w2prev : g_rsxy() * w2prev))};
+                    sr = cfl_rate_f32<NV, NDIM>(acc, gas, rw);
+                } else {
+                    double wd[3] = {wx, wy, GEOM == HX_CART ? w2prev : g_rsxy() * w2prev};
+                    sr = cfl_rate<R, NV, NDIM, EOS>(acc, p.gamma, wd, gas);
+                }
                 if (sr < 0.0)
                     p.flag[0] = 1;
                 smax = fmax(smax, sr);
@@ -1012,10 +1133,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 if constexpr (DE)
                     acc[NV - 1] += mu * (pek * (ufx - ufxr));
             } else {
-                dph = NDIM == 3 ? w2k : p.geo.w[2][0];
-                const double ctj = p.geo.ct[jj];
-                dV = p.geo.vr[ii] * ctj * dph;
-                const double rm = p.geo.rf[ii], rp = p.geo.rf[ii + 1];
+                dph = NDIM == 3 ? w2k : g_dph2();
+                const double ctj = g_ctj();
+                dV = g_vrct() * dph;
+                const double rm = g_rm(), rp = g_rp();
                 dSrm = rm * rm * ctj * dph;
                 dSrp = rp * rp * ctj * dph;
                 const double kvd = dtd / dV;
@@ -1081,8 +1202,8 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 } else {
                     const double kvd = dtd / dV;
                     const R kv = N::from_d(kvd);
-                    dStm = p.geo.hr[ii] * p.geo.sf[jj] * dph;
-                    dStp = p.geo.hr[ii] * p.geo.sf[jj + 1] * dph;
+                    dStm = g_hrsm() * dph;
+                    dStp = g_hrsp() * dph;
                     const R tm = N::from_d(dStm), tp = N::from_d(dStp);
 #pragma unroll
                     for (int v = 0; v < NV; v++)
@@ -1103,7 +1224,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 }
                 double Xt, Tt = 0.0, gtg = 0.0;
                 if (NDIM >= 2) {
-                    const double smm = p.geo.sf[jj], spp = p.geo.sf[jj + 1];
+                    const double smm = g_smm(), spp = g_spp();
                     const double ctc = (spp - smm) / ((spp + smm) * dV);
                     gtg = (dStp - dStm) / dV;
                     Xt = 0.5 * ((double)Fy[2] + (double)Fyu[2]);
@@ -1146,8 +1267,14 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     Un[(long long)v * p.plane + off] = acc[v];
-                double wd[3] = {wx, wy, 0.0};
-                const double sr = cfl_rate<R, NV, NDIM, EOS>(acc, p.gamma, wd, gas);
+                double sr;
+                if constexpr (sizeof(R) == 4) {
+                    const float rw[3] = {rwx, rwy, 0.0f};
+                    sr = cfl_rate_f32<NV, NDIM>(acc, gas, rw);
+                } else {
+                    double wd[3] = {wx, wy, 0.0};
+                    sr = cfl_rate<R, NV, NDIM, EOS>(acc, p.gamma, wd, gas);
+                }
                 if (sr < 0.0)
                     p.flag[0] = 1;
                 smax = fmax(smax, sr);

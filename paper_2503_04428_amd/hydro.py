@@ -38,7 +38,7 @@ class HxConfig(C.Structure):
         ("G", C.c_double), ("Mc", C.c_double), ("dual_energy", C.c_int), ("de_eps", C.c_double),
         ("eos", C.c_int), ("eos_R", C.c_double), ("eos_arad", C.c_double),
         ("ni_heating", C.c_int), ("ni_scalar", C.c_int), ("ni_Q", C.c_double * 2), ("ni_tau", C.c_double * 2),
-        ("ni_m", C.c_double),
+        ("ni_m", C.c_double), ("centroid", C.c_int),
     ]
 
 
@@ -151,6 +151,7 @@ def make_config(prob, precision: str | None = None):
         c.ni_Q[i] = float(_opt(prob, "ni_Q", (0.0, 0.0))[i])
         c.ni_tau[i] = float(_opt(prob, "ni_tau", (1.0, 2.0))[i])
     c.ni_m = float(_opt(prob, "ni_m", 1.0))
+    c.centroid = 1 if _opt(prob, "centroid", False) else 0
     return c, faces
 
 
