@@ -181,11 +181,15 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
 // the parameters); SPEC = 4 the gas + radiation EoS (Sect. 2.3, FP64; limiter and Riemann solver
 // from the parameters); SPEC = 5 both (the monitor's P through the EoS; HLLC).
 // TAG only separates otherwise identical instantiations built in different units (with different
-// code-generation options), so that each unit launches its own.
-template <typename R, int NV, int NDIM, int GEOM, int SPEC, int TAG = 0>
+// code-generation options), so that each unit launches its own.  SRC = 0 compiles out the source
+// terms (gravity, 56Ni heating) for Cartesian configurations without them, whose FP64 source
+// state would otherwise hold registers through the whole sweep.
+template <typename R, int NV, int NDIM, int GEOM, int SPEC, int TAG = 0, int SRC = 1>
 __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, NV, NDIM, GEOM, SPEC>::value))
     sweep_kernel(const SweepParams p)
 {
+    static_assert(SRC == 1 || GEOM == HX_CART, "spherical sweeps always carry their geometric sources");
+    const int grav = SRC ? p.gravity : HX_GRAV_NONE;
     using N = Num<R>;
     constexpr int BX = Tile<NDIM>::BX;
     constexpr int BY = Tile<NDIM>::BY;
@@ -254,7 +258,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     const R dt = N::from_d(dtd);
     // 56Ni heating rates at the start and the middle of the step (FP64 forms with the run-time
     // limiter and solver, the internal-energy monitor or the gas + radiation EoS)
-    const bool heat = sizeof(R) == 8 && SPEC != 1 && p.ni >= 0;
+    const bool heat = SRC && sizeof(R) == 8 && SPEC != 1 && p.ni >= 0;
     double h_n = 0.0, h_half = 0.0;
     if (heat) {
         const double t = p.t_in[0];
@@ -324,11 +328,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     const float rwy = sizeof(R) == 4 && NDIM >= 2 ? (float)(1.0 / wy) : 0.0f;
     // gravity of this column's image (z flips handled per plane)
     double gcol[3] = {0.0, 0.0, 0.0};
-    if (p.gravity == HX_GRAV_UNIFORM) {
+    if (grav == HX_GRAV_UNIFORM) {
         gcol[0] = fx ? -p.g0[0] : p.g0[0];
         gcol[1] = fy ? -p.g0[1] : p.g0[1];
         gcol[2] = p.g0[2];
-    } else if (p.gravity != HX_GRAV_NONE) {
+    } else if (grav != HX_GRAV_NONE) {
         gcol[0] = fx ? -p.gr[ii] : p.gr[ii];
     }
 
@@ -711,7 +715,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             w2k = zg[2];
             double wz = GEOM == HX_CART ? w2k : g_rsxy() * w2k;
             lamz = N::from_d(dtd / (2.0 * wz));
-            if (fzk && p.gravity == HX_GRAV_UNIFORM)
+            if (fzk && grav == HX_GRAV_UNIFORM)
                 g[2] = -g[2];
         }
         // primitive v at offset j - 2 along axis a from the plane in LDS (x, y) or the own column (z)
@@ -848,7 +852,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             if constexpr (DE)
                 du[NV - 1] += lamz * (pe_n() * (wm[1 + 2] - wp[1 + 2]));
         }
-        if (p.gravity != HX_GRAV_NONE) {
+        if (grav != HX_GRAV_NONE) {
             // (dt/2) S(U^n) with S = (0, rho g, m.g, 0)
             R hs = R(0.5) * dt;
             R S[5];
@@ -996,7 +1000,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 enk = qcur[NV - 1];
                 alphak = de_alpha<R>(enk, kinetic_energy<R>(qcur), N::from_d(p.de_eps));
             }
-            if (p.gravity != HX_GRAV_NONE) {
+            if (grav != HX_GRAV_NONE) {
                 Sg[1] = (double)u[0] * g[0];
                 Sg[2] = (double)u[0] * g[1];
                 Sg[3] = (double)u[0] * g[2];
@@ -1053,7 +1057,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     if constexpr (DE)
                         acc[NV - 1] += kv * (pe_prev * (ufzlo * dS - ufz * dS));
                 }
-                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH || heat) {
+                if (grav != HX_GRAV_NONE || GEOM == HX_SPH || heat) {
                     double S[5] = {0.0, sg[1], sg[2], sg[3], sg[4]};
                     if (GEOM == HX_SPH) {
                         const double Xp = 0.5 * ((double)fzlo[3] + (double)Fz[3]);
@@ -1253,7 +1257,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 if constexpr (DE)
                     sg[0] = Sg[0];
             } else {
-                if (p.gravity != HX_GRAV_NONE || GEOM == HX_SPH || heat) {
+                if (grav != HX_GRAV_NONE || GEOM == HX_SPH || heat) {
 #pragma unroll
                     for (int v = 1; v < 5; v++)
                         acc[v] = N::from_d((double)acc[v] + dtd * S[v]);

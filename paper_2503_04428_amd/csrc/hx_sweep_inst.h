@@ -19,6 +19,11 @@ static hipError_t go(const SweepParams& p, int geom, hipStream_t s, int* occ)
     };
     if (geom == HX_SPH)
         return run(sweep_kernel<R, NV, NDIM, HX_SPH, SPEC, TAG>);
+    // 3D Cartesian configurations without gravity or heating: the instantiation without sources
+    if constexpr (NDIM == 3) {
+        if (p.gravity == HX_GRAV_NONE && p.ni < 0)
+            return run(sweep_kernel<R, NV, NDIM, HX_CART, SPEC, TAG, 0>);
+    }
     return run(sweep_kernel<R, NV, NDIM, HX_CART, SPEC, TAG>);
 }
 
