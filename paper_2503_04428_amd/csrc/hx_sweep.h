@@ -40,6 +40,15 @@ namespace hx {
 #ifndef HX_MINW2_FP64_NV
 #define HX_MINW2_FP64_NV 5
 #endif
+// face states formed again after the positivity check (rather than kept from it) from this many
+// fields on: keeping them is faster where the registers allow (FP64 Sedov, 7 fields, one wave per
+// SIMD: 2.312 -> 2.145 ms; FP32 Sedov, 7 fields, three waves: 0.859 -> 0.827 ms)
+#ifndef HX_REFORM_FP64_NV
+#define HX_REFORM_FP64_NV 8
+#endif
+#ifndef HX_REFORM_FP32_NV
+#define HX_REFORM_FP32_NV 8
+#endif
 // FP64 sweeps: form the limited slopes again for the face states (1) or hold them (0)
 #ifndef HX_RESLOPE_FP64
 #define HX_RESLOPE_FP64 0
@@ -906,13 +915,11 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 bad = bad || !positive_state<R>(qs);
             }
         }
-        // The face states are formed below one axis at a time, just before their flux.  For few
-        // fields a face state is the check's expression again and the compiler keeps the check's
-        // values; for more (FP64 from 6 fields, FP32 from 7) the fallback zeroes du and the
-        // slopes first, so the states are recomputed rather than held, which spills less
-        // (measured on the 256^3 workloads: FP32 Sedov 1.03 vs 1.05 ms, FP64 5-field quadrants
-        // 1.27 vs 1.46 ms the other way round).
-        constexpr bool REFORM = RESLOPE || NV >= (sizeof(R) == 8 ? 6 : 7);
+        // The face states are formed below one axis at a time, just before their flux.  Up to
+        // 7 fields a face state is the check's expression again and the compiler keeps the
+        // check's values; from 8 fields (HX_REFORM_*_NV) the fallback zeroes du and the slopes
+        // first, so the states are recomputed rather than held, which spills less.
+        constexpr bool REFORM = RESLOPE || NV >= (sizeof(R) == 8 ? HX_REFORM_FP64_NV : HX_REFORM_FP32_NV);
         if (REFORM && bad) {
 #pragma unroll
             for (int v = 0; v < NV; v++) {
