@@ -316,12 +316,21 @@ __device__ __forceinline__ R de_alpha(R e, R ek, R eps)
     return R(0);
 }
 
-// rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division)
+// rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division).  The FP32 form
+// evaluates it in FP64, where the products of its FP32 values are exact: the sign is then the one
+// of the FP64 internal-energy recovery that the Riemann solver applies to the same state, also
+// when the kinetic energy dominates and FP32 arithmetic would cancel.
 template <typename R>
 __device__ __forceinline__ bool positive_state(const R* q)
 {
-    R m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-    return q[0] > R(0) && R(2) * q[0] * q[4] - m2 > R(0);
+    if constexpr (sizeof(R) == 4) {
+        const double r = q[0], m1 = q[1], m2 = q[2], m3 = q[3], e = q[4];
+        const double mm = m1 * m1 + m2 * m2 + m3 * m3;
+        return q[0] > 0.0f && 2.0 * r * e - mm > 0.0;
+    } else {
+        R m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        return q[0] > R(0) && R(2) * q[0] * q[4] - m2 > R(0);
+    }
 }
 
 template <typename R, int NV, bool DE = false, int EOS = 0>
