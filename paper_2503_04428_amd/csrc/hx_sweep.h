@@ -42,9 +42,11 @@ namespace hx {
 #endif
 // face states formed again after the positivity check (rather than kept from it) from this many
 // fields on: keeping them is faster where the registers allow (FP64 Sedov, 7 fields, one wave per
-// SIMD: 2.312 -> 2.145 ms; FP32 Sedov, 7 fields, three waves: 0.859 -> 0.827 ms)
+// SIMD: 2.312 -> 2.145 ms; boosted Sedov with the monitor, 8 fields: 2.510 -> 2.431 ms; wedge, 9
+// fields: 3.280 -> 3.228 ms; FP32 Sedov, 7 fields, three waves: 0.859 -> 0.827 ms), so FP64
+// sweeps always keep them and FP32 sweeps up to 7 fields
 #ifndef HX_REFORM_FP64_NV
-#define HX_REFORM_FP64_NV 8
+#define HX_REFORM_FP64_NV 10
 #endif
 #ifndef HX_REFORM_FP32_NV
 #define HX_REFORM_FP32_NV 8
@@ -915,10 +917,10 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 bad = bad || !positive_state<R>(qs);
             }
         }
-        // The face states are formed below one axis at a time, just before their flux.  Up to
-        // 7 fields a face state is the check's expression again and the compiler keeps the
-        // check's values; from 8 fields (HX_REFORM_*_NV) the fallback zeroes du and the slopes
-        // first, so the states are recomputed rather than held, which spills less.
+        // The face states are formed below one axis at a time, just before their flux.  Where
+        // registers allow (HX_REFORM_*_NV) a face state is the check's expression again and the
+        // compiler keeps the check's values; otherwise the fallback zeroes du and the slopes first,
+        // so the states are recomputed rather than held, which spills less.
         constexpr bool REFORM = RESLOPE || NV >= (sizeof(R) == 8 ? HX_REFORM_FP64_NV : HX_REFORM_FP32_NV);
         if (REFORM && bad) {
 #pragma unroll
