@@ -248,22 +248,37 @@ def run_learned(hydro, torch, problems, steps, warmup, n, n_ref, zchunk, repeats
 
 
 def sod_exact(hydro, problems):
-    """Sod 1024 (paper App. C.1) to t = 0.2 in FP64 and in the FP32 form: L1 of (rho, u, P) against
-    the exact solution's cell averages (tests/golden/sod1024_exact_t0.2.txt, written from the
-    exact Riemann solver), and the FP32 form's L1 against the FP64 path."""
+    """Sod 1024 (paper App. C.1) to t = 0.2 in FP64 and in the FP32 form, run inside one workgroup
+    (hx_run_1d): L1 of (rho, u, P) against the exact solution's cell averages
+    (tests/golden/sod1024_exact_t0.2.txt, written from the exact Riemann solver), the FP32 form's
+    L1 against the FP64 path, and the zone-cycle rate of that device-side loop beside the host loop
+    (hx_compute_dt + hx_step per step), which is bound by launch latency at this size."""
     import numpy as np
+    import torch
 
     ex = np.loadtxt(os.path.join(ROOT, "tests", "golden", "sod1024_exact_t0.2.txt"))
     prob = problems.sod(1024)
     out, prims = {}, {}
     for form in ("fp64", "fp32"):
-        U, ns = state_at(hydro, prob, 0.2, precision=form)
-        U = U.cpu().numpy().reshape(5, -1)
+        s = hydro.Solver(prob, precision=form)
+        rates = {}
+        for loop in ("host", "device", "device"):  # the second device run is the timed one
+            s.set_state(prob.U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ns = s.run(t_end=0.2) if loop == "host" else s.run_1d(0.2)
+            torch.cuda.synchronize()
+            rates[loop] = prob.ncells * ns / (time.perf_counter() - t0)
+        U = s.state_numpy().reshape(5, -1)
+        s.check()
+        s.close()
         rho = U[0]
         u = U[1] / rho
         p = (prob.gamma - 1.0) * (U[4] - 0.5 * U[1] * u)
         prims[form] = np.stack([rho, u, p], axis=1)
-        out[form] = {"steps": ns, "l1_vs_exact": np.abs(prims[form] - ex).mean(axis=0).tolist()}
+        out[form] = {"steps": ns, "l1_vs_exact": np.abs(prims[form] - ex).mean(axis=0).tolist(),
+                     "zone_cycles_per_s_one_workgroup_loop": rates["device"],
+                     "zone_cycles_per_s_host_loop": rates["host"]}
     out["fp32"]["l1_vs_fp64"] = np.abs(prims["fp32"] - prims["fp64"]).mean(axis=0).tolist()
     out["fields"] = ["rho", "u", "P"]
     out["note"] = "L1 = mean over the 1024 cells of |q - q_exact| (the integral over [0, 1])"
@@ -529,7 +544,9 @@ def main():
         log("accuracy against exact solutions ...")
         accuracy = {"sod": sod_exact(hydro, problems), "sedov": sedov_exact(hydro, problems)}
         log(f"sod L1 rho: fp64 {accuracy['sod']['fp64']['l1_vs_exact'][0]:.3e}, fp32 "
-            f"{accuracy['sod']['fp32']['l1_vs_exact'][0]:.3e}; sedov radius error fp64 "
+            f"{accuracy['sod']['fp32']['l1_vs_exact'][0]:.3e}; sod fp64 zone-cycles/s one-workgroup loop "
+            f"{accuracy['sod']['fp64']['zone_cycles_per_s_one_workgroup_loop']:.3e}, host loop "
+            f"{accuracy['sod']['fp64']['zone_cycles_per_s_host_loop']:.3e}; sedov radius error fp64 "
             f"{accuracy['sedov']['fp64']['radius_rel_error']:.3e}")
 
     if args.copy_ref_mib > 0:

@@ -148,6 +148,21 @@ hx_status hx_step(hx_ctx *ctx, double dt);
  * hx_compute_dt_device), so that a time loop needs no host synchronisation.  Asynchronous. */
 hx_status hx_step_device(hx_ctx *ctx, const double *d_dt);
 
+/* Run a 1D problem from time t0 with CFL steps (the last one clipped to t_end) until t_end or
+ * max_steps steps, inside one workgroup on the device: the state stays on chip, each step takes
+ * the CFL time step and the MUSCL-Hancock step of hx_compute_dt / hx_step (FP64: the same results,
+ * bit for bit, as that host loop; FP32 form: the same to FP32 rounding, since the compiler may
+ * contract FP32 products and sums differently in the two kernels), and no kernel is launched and nothing synchronises per step (Sect.
+ * 3.2; the Sod tube of App. C.1 is this size).  For one Cartesian row (ndim 1, n[1] = 1) of at
+ * most 2046 cells whose primitives and face states, 3 nvar (n + 4) values of 8 bytes (FP64) or 4
+ * (FP32 form), fit the device's LDS with 512 bytes to spare (160 KiB on gfx950: at most 1357 cells
+ * with 5 fields in FP64, 2046 in FP32), with the ideal gas and no gravity, heating,
+ * internal-energy monitor or learned limiter; HX_EINVAL otherwise, or for
+ * a non-finite t0 or t_end or max_steps < 1; HX_ESTATE before hx_set_state.  Writes the final time
+ * to *h_t and the number of steps to *h_steps; synchronises and reports HX_ENONPHYS like
+ * hx_compute_dt. */
+hx_status hx_run_1d(hx_ctx *ctx, double t0, double t_end, int max_steps, double *h_t, int *h_steps);
+
 /* Conserved totals sum_cells U_v dV (FP64), nvar values to host h_tot.  Synchronises; returns
  * HX_ENONPHYS like hx_compute_dt. */
 hx_status hx_totals(hx_ctx *ctx, double *h_tot);

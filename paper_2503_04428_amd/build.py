@@ -11,6 +11,8 @@ Each HIP translation unit is compiled separately (no relocatable device code):
   hx_reduce.hip      dt / totals / enclosed-mass reductions, -ffp-contract=off
   hx_shift.hip       grid shift along axis 0 (conservative remap), -ffp-contract=off
   hx_mlp.hip         learned limiter: BF16-MFMA evaluation, training samples, FP32 training
+  hx_run1d_fp64.hip  persistent one-workgroup run of a 1D problem to t_end, -ffp-contract=off
+  hx_run1d_fp32.hip  the same for the FP32 form (the FP32 sweep's flags)
   hx_abi.hip         C ABI host code
 Packed FP32 instructions are disabled for all device code.
 """
@@ -46,6 +48,8 @@ UNITS = {
     "hx_reduce.hip": ["-ffp-contract=off"],
     "hx_shift.hip": ["-ffp-contract=off"],
     "hx_mlp.hip": ["-ffp-contract=off"],
+    "hx_run1d_fp64.hip": ["-ffp-contract=off"],
+    "hx_run1d_fp32.hip": [],
     "hx_abi.hip": ["-ffp-contract=off"],
 }
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "hx_launch.h"
+#include "hx_run1d.h"
 
 namespace {
 
@@ -73,7 +74,7 @@ struct Layout {
     size_t state[2];
     size_t tab[3][4];  // cm, cp, w, kap per axis
     size_t rabs, sabs, rf, vr, hr, ct, sf;
-    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp, time, xfaces;
+    size_t gr, menc, shell, partial, dtpart, dt, flag, tot, mlp, time, xfaces, run;
     size_t total;
     int ntab[3];
     int nchunk, nred;
@@ -238,6 +239,7 @@ Layout layout(const hx_config* c)
     L.tot = take(sizeof(double) * nv);
     L.mlp = take(sizeof(float) * HX_MLP_NPARAM);
     L.time = take(sizeof(double));  // the decay clock of the 56Ni heating
+    L.run = take(2 * sizeof(double));  // final time and step count of hx_run_1d
     L.xfaces = take(sizeof(double) * (c->n[0] + 1 + 2 * c->nghost));  // axis-0 faces (grid shift)
     L.total = off;
     return L;
@@ -790,6 +792,57 @@ hx_status hx_step_device(hx_ctx* x, const double* d_dt)
     if (!x || !d_dt)
         return fail(HX_EINVAL, "null argument");
     return enqueue_step(x, 0.0, d_dt);
+}
+
+hx_status hx_run_1d(hx_ctx* x, double t0, double t_end, int max_steps, double* h_t, int* h_steps)
+{
+    if (!x || !h_t || !h_steps)
+        return fail(HX_EINVAL, "null argument");
+    if (!x->have_state)
+        return fail(HX_ESTATE, "run before set_state");
+    const hx_config& c = x->cfg;
+    if (c.ndim != 1 || c.geom != HX_GEOM_CART || c.n[1] != 1)
+        return fail(HX_EINVAL, "hx_run_1d runs one Cartesian 1D row (ndim 1, n[1] = 1)");
+    if (c.n[0] > hx::RUN1D_MAX_CELLS)
+        return fail(HX_EINVAL, "hx_run_1d holds at most %d cells (got %d)", hx::RUN1D_MAX_CELLS, c.n[0]);
+    if (c.gravity != HX_GRAVITY_NONE || c.dual_energy || c.eos != HX_EOS_GAS || c.ni_heating ||
+        c.limiter == HX_LIMITER_MLP)
+        return fail(HX_EINVAL, "hx_run_1d supports the ideal gas without gravity, heating, the internal-energy "
+                               "monitor or the learned limiter");
+    if (!std::isfinite(t0) || !std::isfinite(t_end) || max_steps < 1)
+        return fail(HX_EINVAL, "need finite t0, t_end and max_steps >= 1");
+    int dev = 0, maxlds = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lds = hx::run1d_lds_bytes(c.n[0], x->nvar, x->fp32) + 512;
+    if (lds > (size_t)maxlds)
+        return fail(HX_EINVAL, "hx_run_1d needs %zu bytes of LDS for %d cells and %d fields, the device has %d",
+                    lds, c.n[0], x->nvar, maxlds);
+    hx::Run1dParams p;
+    p.U = x->state[x->cur];
+    p.n = c.n[0];
+    p.ng = x->ng;
+    p.plane = x->ncells;
+    p.gamma = c.gamma;
+    p.cfl = c.cfl;
+    p.limiter = c.limiter;
+    p.riemann = c.riemann;
+    p.bc0[0] = c.bc[0][0];
+    p.bc0[1] = c.bc[0][1];
+    p.geo = x->geo;
+    p.flag = at<int>(x, x->L.flag);
+    p.out = at<double>(x, x->L.run);
+    p.t0 = t0;
+    p.t_end = t_end;
+    p.max_steps = max_steps;
+    HIPCHECK(hx::launch_run1d(p, x->nvar, x->fp32, x->stream));
+    x->dtpart_valid = false;  // the sweep's CFL maxima no longer describe the state
+    double out[2];
+    HIPCHECK(hipMemcpyAsync(out, p.out, sizeof out, hipMemcpyDeviceToHost, x->stream));
+    const hx_status st = sync_check(x);
+    *h_t = out[0];
+    *h_steps = (int)out[1];
+    return st;
 }
 
 hx_status hx_totals(hx_ctx* x, double* h_tot)

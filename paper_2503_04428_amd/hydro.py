@@ -56,7 +56,7 @@ _lib = None
 
 # names of the exported entry points, as declared in include/hydro.h
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
-           "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_totals", "hx_check", "hx_set_mlp",
+           "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_run_1d", "hx_totals", "hx_check", "hx_set_mlp",
            "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_shift_grid", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
            "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_grad_noalloc", "hx_mlp_adam", "hx_last_error",
            "hx_destroy"]
@@ -82,6 +82,7 @@ def load_library():
     L.hx_compute_dt_device.argtypes = [vp, vp]
     L.hx_step.argtypes = [vp, C.c_double]
     L.hx_step_device.argtypes = [vp, vp]
+    L.hx_run_1d.argtypes = [vp, C.c_double, C.c_double, C.c_int, _DP, C.POINTER(C.c_int)]
     L.hx_totals.argtypes = [vp, _DP]
     L.hx_check.argtypes = [vp]
     L.hx_set_mlp.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
@@ -282,6 +283,15 @@ class Solver:
             t += dt
             steps += 1
         return t, steps
+
+    def run_1d(self, t_end: float, max_steps: int = 1 << 30, t0: float = 0.0):
+        """The same time loop as run(t_end) for a 1D row, inside one workgroup on the device (no
+        launch or synchronisation per step); returns (t, steps)."""
+        t = C.c_double(0.0)
+        n = C.c_int(0)
+        self._call(self.L.hx_run_1d(self.ctx, C.c_double(float(t0)), C.c_double(float(t_end)), int(max_steps),
+                                    C.byref(t), C.byref(n)))
+        return t.value, n.value
 
     def totals(self) -> np.ndarray:
         out = np.zeros(self.nvar)
