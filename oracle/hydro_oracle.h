@@ -10,9 +10,9 @@
  * library.
  *
  * Units of the paper followed here:
- *   Sect. 2.1 (eqs. continuity, momentum, energy, passive scalar; 56Ni decay heating,
- *   eq. heating_ni), Sect. 2.2 (uniform / point / enclosed-mass gravity), Sect. 2.3 (ideal-gas
- *   and gas + radiation EoS), Sect. 2.5 (internal-energy monitor),
+ *   Sect. 2.1 (eqs. continuity, momentum, energy with its heating term, passive scalar),
+ *   Sect. 2.2 (uniform / point / enclosed-mass gravity), Sect. 2.3 (ideal-gas and gas + radiation
+ *   EoS), Sect. 2.4 (56Ni decay heating, eq. heating_ni), Sect. 2.5 (internal-energy monitor),
  *   Sect. 3.1.1 (mesh, dS, dV), Sect. 3.1.2 (spherical momentum sources,
  *   eq. source_terms_1 and the theta counterpart), Sect. 3.2 (slope-limited
  *   reconstruction, Hancock half step, Godunov update eq. godunov, HLL/HLLC,
