@@ -126,12 +126,17 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(const double* __restr
 
 // ---------------------------------------------------------------------------- training
 
-__device__ __forceinline__ float gelu_exact_tanh(float z, float& dg)
+// tanh-form GELU and its derivative, the value in the deployed form z s with s = 1 / (1 + 2^(z (G1 +
+// G3 z^2))) (gelu_f of the fused evaluation, the same operations); the derivative of z s(y(z)),
+// y = 2 k (z + 0.044715 z^3), is s + z s (1 - s) y'(z)
+__device__ __forceinline__ float gelu_train(float z, float& dg)
 {
+    constexpr float G1 = (float)(-2.0 * 0.7978845608028654 * 1.4426950408889634);
+    constexpr float G3 = (float)(-2.0 * 0.7978845608028654 * 0.044715 * 1.4426950408889634);
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * (G1 + G3 * z * z)));
     const float k = 0.7978845608028654f;
-    const float th = tanhf(k * (z + 0.044715f * z * z * z));
-    dg = 0.5f * (1.0f + th) + 0.5f * z * (1.0f - th * th) * k * (1.0f + 3.0f * 0.044715f * z * z);
-    return 0.5f * z * (1.0f + th);
+    dg = sg + z * sg * (1.0f - sg) * (2.0f * k) * (1.0f + 3.0f * 0.044715f * z * z);
+    return z * sg;
 }
 
 __device__ __forceinline__ float wave_sum_f(float v)
@@ -145,7 +150,10 @@ __device__ __forceinline__ float wave_sum_f(float v)
 constexpr int GB = 256;  // threads per gradient block
 constexpr int GW = GB / 64;  // waves per gradient block
 
-// Per-sample FP32 forward/backward of L = sum wt (phi a - t)^2 (unnormalised); per-block sums of
+// Per-sample FP32 forward/backward of L = sum wt (phi a - t)^2 (unnormalised), with FP32 parameters
+// and activations and the GELU and output sigmoid in the forms the fused BF16 evaluation uses
+// (exp2 and reciprocal); the BF16 roundings of the deployed network are left out of training (the
+// deployed loss on the training samples is measured beside the FP32 one); per-block sums of
 // the 1249 gradients, of the loss and of the weights go to part[block][1251].  Every wave adds its
 // wave sums into its own LDS row (one lane writes, so each row is summed in sample order), and the
 // rows are added in wave order at the end: the result does not depend on wave timing.
@@ -188,18 +196,18 @@ __global__ void __launch_bounds__(GB) mlp_grad_kernel(const float* __restrict__ 
             float s = b1[o];
             for (int i = 0; i < 4; i++)
                 s += W1[o * 4 + i] * xi[i];
-            h1[o] = gelu_exact_tanh(s, g1[o]);
+            h1[o] = gelu_train(s, g1[o]);
         }
         for (int o = 0; o < 32; o++) {
             float s = b2[o];
             for (int i = 0; i < 32; i++)
                 s += W2[o * 32 + i] * h1[i];
-            h2[o] = gelu_exact_tanh(s, g2[o]);
+            h2[o] = gelu_train(s, g2[o]);
         }
         float z = b3;
         for (int i = 0; i < 32; i++)
             z += w3[i] * h2[i];
-        const float phi = 2.0f / (1.0f + expf(-z));
+        const float phi = 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
         const float err = phi * ae - te;
         const float loss = we * err * err;
         const float dz = 2.0f * we * err * ae * phi * (1.0f - 0.5f * phi);

@@ -124,6 +124,25 @@ def baseline_loss(samples, phi_rule: str = "vanleer"):
     return float(((wt * (phi * a - t) ** 2).sum() / wt.sum()).item())
 
 
+def deployed_loss(weights, samples, device="cuda"):
+    """Loss of the network as the sweep evaluates it (BF16 parameters, inputs and first hidden layer
+    on the matrix cores, hx_mlp_eval) on the samples; training itself runs in FP32, so this is what
+    the BF16 roundings change (the weighted sum is evaluation only)."""
+    import torch
+
+    x, a, t, wt = samples
+    phi = hydro.mlp_eval(torch.as_tensor(np.asarray(weights, dtype=np.float32), device=device), x)
+    return float(((wt * (phi * a - t) ** 2).sum() / wt.sum()).item())
+
+
+def training_loss(weights, samples, device="cuda"):
+    """Loss of the FP32 training forward (hx_mlp_grad) on the samples."""
+    x = samples[0]
+    tr = hydro.MlpTrainer(np.asarray(weights, dtype=np.float32), x.shape[0], device=device)
+    _, loss = tr.gradient(*samples)
+    return float(loss.item())
+
+
 def coarse_error(weights, nprob: int = 256, ncoarse: int = 256, ratio: int = 4, t_end: float = 0.05,
                  seed: int = 5000, device="cuda"):
     """L1 errors of the coarse FP32 runs (learned limiter and van Leer) and the FP64 van Leer run

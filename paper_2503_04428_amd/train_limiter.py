@@ -3,7 +3,8 @@
     python -m paper_2503_04428_amd.train_limiter [--out DIR] [--nprob 2048] [--steps 4000]
 
 Writes DIR/mlp_limiter_weights.npy (FP32, 1249 values) and DIR/mlp_limiter_training.json (data
-recipe, optimiser settings, loss history, the van Leer loss on the same samples, and the coarse-grid
+recipe, optimiser settings, loss history, the loss of the deployed BF16 evaluation and of van Leer
+on the same samples, and the coarse-grid
 L1 errors of learned vs van Leer against the restricted fine FP64 solution on held-out problems).
 """
 import argparse
@@ -38,8 +39,9 @@ def main(argv=None):
     print(f"loss of classical limiters on the samples: {base}", flush=True)
     t1 = time.time()
     w, log = learned.train(samples, steps=args.steps, batch=args.batch, lr=args.lr, seed=args.seed)
-    print(f"trained {args.steps} steps in {time.time() - t1:.1f} s, full loss {log['final_full_loss']:.5f}",
-          flush=True)
+    log["deployed_full_loss"] = learned.deployed_loss(w, samples)
+    print(f"trained {args.steps} steps in {time.time() - t1:.1f} s, full loss {log['final_full_loss']:.5f} "
+          f"(the deployed BF16 evaluation: {log['deployed_full_loss']:.5f})", flush=True)
     t2 = time.time()
     ev = learned.coarse_error(w, nprob=args.eval_nprob, ncoarse=args.ncoarse, ratio=args.ratio, t_end=0.05,
                               seed=5000)

@@ -213,6 +213,29 @@ def test_training_reduces_loss(env):
     assert last < 0.8 * first, log["loss_log"]
 
 
+def test_deployed_rounding_keeps_the_training_loss(env):
+    """Training runs in FP32; the sweep evaluates the network with BF16 parameters, inputs and first
+    hidden layer.  On samples drawn with the training recipe from held-out problems, the loss of the
+    deployed evaluation stays within 1 % of the FP32 training forward's, and both stay below the
+    loss of van Leer's slope on the same samples."""
+    H, torch = env
+    from paper_2503_04428_amd import learned
+    try:
+        w = learned.load_weights()
+    except OSError:
+        pytest.skip("no trained weights")
+    announce("deployed BF16 loss vs FP32 training loss")
+    samples, info = learned.generate_samples(nprob=128, ncoarse=256, ratio=4, times=(0.02, 0.04, 0.06), seed=4321)
+    assert info["samples"] > 10000
+    l32 = learned.training_loss(w, samples)
+    ldep = learned.deployed_loss(w, samples)
+    lvl = learned.baseline_loss(samples, "vanleer")
+    print(f"loss on {info['samples']} held-out samples: FP32 training forward {l32:.5f}, deployed BF16 "
+          f"{ldep:.5f} ({(ldep - l32) / l32:+.2%}), van Leer {lvl:.5f}")
+    assert abs(ldep - l32) <= 0.01 * l32
+    assert ldep < lvl and l32 < lvl
+
+
 @pytest.mark.parametrize("t_end", [0.05, 0.1])
 def test_trained_network_gains_over_vanleer(env, t_end):
     """What the trained network gains: on held-out 1D Riemann problems (a seed that neither the
