@@ -20,7 +20,10 @@ def kernel_source_hash() -> str:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
-    flags = {"common": B.COMMON, "units": {k: v for k, v in sorted(B.UNITS.items()) if k.startswith("hx_sweep")}}
+    # the include paths are absolute: hash them relative to the repository root, so that the same
+    # sources give the same hash wherever the tree sits
+    common = [f.replace(B.ROOT, "<root>") for f in B.COMMON]
+    flags = {"common": common, "units": {k: v for k, v in sorted(B.UNITS.items()) if k.startswith("hx_sweep")}}
     h.update(json.dumps(flags, sort_keys=True).encode())
     return h.hexdigest()[:16]
 

@@ -50,3 +50,23 @@ def test_traffic_record():
     from paper_2503_04428_amd.srchash import kernel_source_hash
     expect = rec["fp64_bytes"] if rec["source_hash"] == kernel_source_hash() else None
     assert bench.recorded_traffic("fp64") == expect
+
+
+def test_source_hash_does_not_depend_on_the_tree_location(tmp_path):
+    """The hash that ties the traffic record to the kernel sources must be the same wherever the
+    repository sits (the bench runs from another path than the one the record was written in)."""
+    import shutil
+    import subprocess
+    import sys
+
+    from paper_2503_04428_amd.srchash import kernel_source_hash
+
+    pkg = os.path.join(ROOT, "paper_2503_04428_amd")
+    dst = tmp_path / "elsewhere"
+    dst.mkdir()
+    shutil.copytree(pkg, dst / "paper_2503_04428_amd",
+                    ignore=shutil.ignore_patterns("_build*", "*.so", "__pycache__"))
+    out = subprocess.run([sys.executable, "-c",
+                          "from paper_2503_04428_amd.srchash import kernel_source_hash as k; print(k())"],
+                         cwd=dst, capture_output=True, text=True, check=True).stdout.strip()
+    assert out == kernel_source_hash()
