@@ -235,26 +235,36 @@ __device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w, R* T = n
 }
 
 // CFL signal rate of the FP32 form, sum_d (|u_d| + c_s) rw_d with rw_d the reciprocal widths rounded
-// once to FP32: the internal energy E - |m|^2/(2 rho) is recovered in FP64 (to_prim), the rest is
-// FP32; the maximum over cells and the time step cfl / max stay FP64.  A negative value marks a
-// non-physical state.  The sweep's store and the standalone CFL kernel both use it, so the time
-// step of a state does not depend on which of them computed it.
+// once to FP32: the internal energy E - |m|^2/(2 rho) is recovered in FP64 (as in to_prim), the
+// rest is FP32; the maximum over cells and the time step cfl / max stay FP64.  A negative value
+// marks a non-physical state.  The sweep's store and the standalone CFL kernel both use it, and it
+// is rounded as written whatever the unit's contraction setting, so the time step of a state does
+// not depend on which of them computed it.
 template <int NV, int NDIM>
 __device__ __forceinline__ double cfl_rate_f32(const float* q, const Gas<float>& g, const float* rw)
 {
+    // rounded as written whatever the unit's contraction setting: the primitives are the
+    // operations of to_prim<float> (FP64 island for the internal energy), repeated here so that
+    // the FP32 sweeps keep contraction in their own conversions
+#pragma clang fp contract(off)
     bool fin = true;
 #pragma unroll
     for (int v = 0; v < NV; v++)
         fin = fin && isfinite(q[v]);
-    float w[NV];
-    const float inv = to_prim<float, NV>(g, q, w);
-    if (!fin || !(q[0] > 0.0f) || !(w[4] > 0.0f))
+    const float rho = q[0];
+    double id = (double)__builtin_amdgcn_rcpf(rho);
+    id = id * (2.0 - (double)rho * id);
+    const double m1 = q[1], m2 = q[2], m3 = q[3];
+    const double ke = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * id;
+    const float inv = (float)id;
+    const float p = (float)((double)g.gm1 * ((double)q[4] - ke));
+    if (!fin || !(rho > 0.0f) || !(p > 0.0f))
         return -1.0;
-    const float cs = __builtin_amdgcn_sqrtf(g.gamma * w[4] * inv);
+    const float cs = __builtin_amdgcn_sqrtf(g.gamma * p * inv);
     float s = 0.0f;
 #pragma unroll
     for (int d = 0; d < NDIM; d++)
-        s += (fabsf(w[1 + d]) + cs) * rw[d];
+        s += (fabsf(q[1 + d] * inv) + cs) * rw[d];
     return (double)s;
 }
 

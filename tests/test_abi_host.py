@@ -43,7 +43,8 @@ def test_workspace_bytes_for_the_workloads():
 
 
 @pytest.mark.parametrize("bad", ["ndim", "nghost", "faces", "periodic", "gravity", "r0", "nscalar", "mlp",
-                                 "eos_kind", "eos_fp32", "eos_R", "eos_mlp", "ni_fp32", "ni_scalar", "ni_tau"])
+                                 "eos_kind", "eos_fp32", "eos_R", "eos_mlp", "ni_fp32", "ni_scalar", "ni_tau",
+                                 "empty_axis", "short_axis", "empty_batch", "inactive_axis"])
 def test_invalid_configurations_are_rejected(bad):
     pr = P.random_periodic(n=(6, 5, 4), ndim=3, nscalar=1)
     if bad == "ndim":
@@ -81,9 +82,21 @@ def test_invalid_configurations_are_rejected(bad):
         pr = P.with_gas_rad(pr).with_(eos_R=0.0)
     elif bad == "eos_mlp":
         pr = P.with_gas_rad(pr).with_(limiter="mlp", ng=3, precision="fp32")
+    elif bad == "empty_batch":
+        pr = P.sod(64)
+    elif bad == "inactive_axis":
+        pr = P.random_periodic(n=(6, 5), ndim=2, nscalar=1)
     L = H.load_library()
     c, keep = H.make_config(pr)
     if bad == "eos_kind":
         c.eos = 2
+    elif bad == "empty_axis":  # no cells on an active axis
+        c.n[0] = 0
+    elif bad == "short_axis":  # fewer cells than ghost layers
+        c.n[2] = 1
+    elif bad == "empty_batch":  # a batch of zero 1D rows
+        c.n[1] = 0
+    elif bad == "inactive_axis":  # cells on an axis beyond ndim
+        c.n[2] = 3
     assert L.hx_workspace_bytes(C.byref(c)) == 0
     assert len(L.hx_last_error()) > 0
