@@ -68,8 +68,7 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                          "(python -c 'import __graft_entry__ as g; g.build()')")
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2503_04428_amd.build")
     L = C.CDLL(LIB_PATH)
     cfgp = C.POINTER(HxConfig)
     vp = C.c_void_p
