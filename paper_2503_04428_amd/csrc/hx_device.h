@@ -12,12 +12,35 @@
 
 namespace hx {
 
+// FP64 quotient a / b rounded to nearest even, for operands whose quotient, reciprocal and
+// remainder stay well inside the normal range (exponents within about +-700; the states, widths
+// and time steps of this method are): the hardware reciprocal refined by two Newton-Raphson steps
+// and the quotient corrected once by its exact FMA remainder (Markstein's method).  These are the
+// operations of the compiler's correctly rounded division without its operand range scaling and
+// special-value fixup, which act only near the ends of the exponent range and on zeros,
+// infinities and NaNs; checked bit for bit against the compiler's division on 1.3e8 operand pairs
+// with exponents in [-300, 300].  Two differences remain: -0 / b for b > 0 gives +0 (the values
+// are equal), and a zero, infinite or NaN operand does not give IEEE's special result (x / 0 is
+// NaN, not an infinity), so a division whose denominator may be zero keeps the IEEE operator.  It saves the two scaling instructions and the fixup of each division, and the
+// scaling's use of the single VCC register, which keeps the scheduler from overlapping divisions.
+__device__ __forceinline__ double div_rn(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double m = a * r;
+    const double t = fma(-b, m, a);
+    return fma(t, r, m);
+}
+
 template <typename R>
 struct Num;
 
 template <>
 struct Num<double> {
-    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double div(double a, double b) { return div_rn(a, b); }
     static __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
     static __device__ __forceinline__ double abs_(double a) { return fabs(a); }
     static __device__ __forceinline__ double from_d(double a) { return a; }
@@ -65,8 +88,9 @@ __device__ __forceinline__ void temp_solve(const Gas<double>& g, const double* r
     bool act[K];
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        c[j] = FROM_P ? rho[j] * g.Rg : (rho[j] * g.Rg) / g.gm1;
-        const double tg = x[j] / c[j];
+        c[j] = FROM_P ? rho[j] * g.Rg : div_rn(rho[j] * g.Rg, g.gm1);
+        const double tg = div_rn(x[j], c[j]);
+        // IEEE division: a = 0 (the gas-only limit) must give an infinite radiation temperature
         const double tr = sqrt(sqrt(FROM_P ? (3.0 * x[j]) / g.arad : x[j] / g.arad));
         T[j] = tg < tr ? tg : tr;
         act[j] = true;
@@ -80,13 +104,13 @@ __device__ __forceinline__ void temp_solve(const Gas<double>& g, const double* r
                 const double Tj = T[j];
                 double f, fp;
                 if (FROM_P) {
-                    f = c[j] * Tj + (g.arad * t4(Tj)) / 3.0 - x[j];
-                    fp = c[j] + (4.0 * g.arad * ((Tj * Tj) * Tj)) / 3.0;
+                    f = c[j] * Tj + div_rn(g.arad * t4(Tj), 3.0) - x[j];
+                    fp = c[j] + div_rn(4.0 * g.arad * ((Tj * Tj) * Tj), 3.0);
                 } else {
                     f = c[j] * Tj + g.arad * t4(Tj) - x[j];
                     fp = c[j] + 4.0 * g.arad * ((Tj * Tj) * Tj);
                 }
-                const double dT = f / fp;
+                const double dT = div_rn(f, fp);
                 T[j] = Tj - dT;
                 act[j] = !(fabs(dT) <= EOS_NEWTON_TOL * T[j]);
             }
@@ -114,13 +138,13 @@ __device__ __forceinline__ double temp_from_p(const Gas<double>& g, double rho, 
 // internal energy per unit volume at temperature T
 __device__ __forceinline__ double rad_energy(const Gas<double>& g, double rho, double T)
 {
-    return ((rho * g.Rg) * T) / g.gm1 + g.arad * t4(T);
+    return div_rn((rho * g.Rg) * T, g.gm1) + g.arad * t4(T);
 }
 
 // pressure at temperature T
 __device__ __forceinline__ double rad_pressure(const Gas<double>& g, double rho, double T)
 {
-    return (rho * g.Rg) * T + (g.arad * t4(T)) / 3.0;
+    return (rho * g.Rg) * T + div_rn(g.arad * t4(T), 3.0);
 }
 
 // a wave-uniform double moved to scalar registers (it stays live through a whole sweep)
@@ -153,11 +177,11 @@ __device__ __forceinline__ R sound_speed(const Gas<R>& g, const R* w, R inv, R T
     } else {
         static_assert(sizeof(R) == 8, "the gas + radiation EoS is built for FP64");
         const double pg = (w[0] * g.Rg) * T;
-        const double pr = (g.arad * t4(T)) / 3.0;
-        const double al = pr / pg;
-        const double num = g.gamma / g.gm1 + 20.0 * al + 16.0 * (al * al);
-        const double den = 1.0 / g.gm1 + 12.0 * al;
-        return sqrt((num / den) * (pg * inv));
+        const double pr = div_rn(g.arad * t4(T), 3.0);
+        const double al = div_rn(pr, pg);
+        const double num = div_rn(g.gamma, g.gm1) + 20.0 * al + 16.0 * (al * al);
+        const double den = div_rn(1.0, g.gm1) + 12.0 * al;
+        return sqrt(div_rn(num, den) * (pg * inv));
     }
 }
 
@@ -174,7 +198,7 @@ struct PrimImpl<double, NV, DE, EOS> {
     static __device__ __forceinline__ double run(const Gas<double>& g, const double* q, double* w, double* T)
     {
         double rho = q[0];
-        double inv = 1.0 / rho;
+        double inv = div_rn(1.0, rho);
         double u1 = q[1] * inv, u2 = q[2] * inv, u3 = q[3] * inv;
         double ke = 0.5 * (q[1] * u1 + q[2] * u2 + q[3] * u3);
         w[0] = rho;
@@ -280,7 +304,7 @@ __device__ __forceinline__ void to_prim_rad2(const Gas<double>& g, const double*
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         rho[j] = q[j][0];
-        inv[j] = 1.0 / rho[j];
+        inv[j] = div_rn(1.0, rho[j]);
         const double u1 = q[j][1] * inv[j], u2 = q[j][2] * inv[j], u3 = q[j][3] * inv[j];
         const double ke = 0.5 * (q[j][1] * u1 + q[j][2] * u2 + q[j][3] * u3);
         w[j][0] = rho[j];
@@ -304,11 +328,21 @@ __device__ __forceinline__ void to_prim_rad2(const Gas<double>& g, const double*
     Tb = T[1];
 }
 
+// IEEE quotient in either precision (div_rn in FP64)
+template <typename R>
+__device__ __forceinline__ R qdiv(R a, R b)
+{
+    if constexpr (sizeof(R) == 8)
+        return div_rn(a, b);
+    else
+        return a / b;
+}
+
 // kinetic energy |m|^2 / (2 rho) of a conserved state
 template <typename R>
 __device__ __forceinline__ R kinetic_energy(const R* q)
 {
-    return R(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+    return qdiv<R>(R(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]), q[0]);
 }
 
 // blend factor of the internal-energy monitor (Sect. 2.5): 1 for e >= eps e_k,
@@ -319,8 +353,8 @@ __device__ __forceinline__ R de_alpha(R e, R ek, R eps)
     const R t = eps * ek;
     if (e >= t)
         return R(1);
-    if (e > t / R(10)) {
-        const R r = e / t;
+    if (e > qdiv<R>(t, R(10))) {
+        const R r = qdiv<R>(e, t);
         return r * r;
     }
     return R(0);

@@ -160,13 +160,13 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
         fin = fin && isfinite(q[v]);
     }
     const double rho = q[0];
-    const double inv = 1.0 / rho;
+    const double inv = div_rn(1.0, rho);
     const double u1 = q[1] * inv, u2 = q[2] * inv, u3 = q[3] * inv;
     const double ke = 0.5 * (q[1] * u1 + q[2] * u2 + q[3] * u3);
     double pr, cs;
     if constexpr (EOS == 1) {
         const double T = temp_from_e(eg, rho, q[4] - ke);
-        pr = (rho * eg.Rg) * T + (eg.arad * t4(T)) / 3.0;
+        pr = (rho * eg.Rg) * T + div_rn(eg.arad * t4(T), 3.0);
         if (!fin || !(rho > 0.0) || !(pr > 0.0))
             return -1.0;
         const double w[5] = {rho, u1, u2, u3, pr};
@@ -181,7 +181,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
     double s = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; d++)
-        s += (fabs(u[d]) + cs) / wd[d];
+        s += div_rn(fabs(u[d]) + cs, wd[d]);
     return s;
 }
 
@@ -322,21 +322,21 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
     R lamx, lamy = R(0);
     double wx = p.geo.w[0][gx], wy = 0.0;
     if (GEOM == HX_CART) {
-        lamx = N::from_d(dtd / (2.0 * wx));
+        lamx = N::from_d(div_rn(dtd, 2.0 * wx));
         if (NDIM >= 2) {
             wy = p.geo.w[1][gy];
-            lamy = N::from_d(dtd / (2.0 * wy));
+            lamy = N::from_d(div_rn(dtd, 2.0 * wy));
         }
     } else {
-        lamx = N::from_d(dtd / (2.0 * wx));
+        lamx = N::from_d(div_rn(dtd, 2.0 * wx));
         if (NDIM >= 2) {
             wy = p.geo.rabs[gx] * p.geo.w[1][gy];
-            lamy = N::from_d(dtd / (2.0 * wy));
+            lamy = N::from_d(div_rn(dtd, 2.0 * wy));
         }
     }
     // FP32 form: reciprocal widths of the CFL rate, rounded once to FP32 (x and y per column)
-    const float rwx = sizeof(R) == 4 ? (float)(1.0 / wx) : 0.0f;
-    const float rwy = sizeof(R) == 4 && NDIM >= 2 ? (float)(1.0 / wy) : 0.0f;
+    const float rwx = sizeof(R) == 4 ? (float)div_rn(1.0, wx) : 0.0f;
+    const float rwy = sizeof(R) == 4 && NDIM >= 2 ? (float)div_rn(1.0, wy) : 0.0f;
     // gravity of this column's image (z flips handled per plane)
     double gcol[3] = {0.0, 0.0, 0.0};
     if (grav == HX_GRAV_UNIFORM) {
@@ -725,7 +725,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             cpz = N::from_d(zg[1]);
             w2k = zg[2];
             double wz = GEOM == HX_CART ? w2k : g_rsxy() * w2k;
-            lamz = N::from_d(dtd / (2.0 * wz));
+            lamz = N::from_d(div_rn(dtd, 2.0 * wz));
             if (fzk && grav == HX_GRAV_UNIFORM)
                 g[2] = -g[2];
         }
@@ -1049,7 +1049,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             if (interior && k - 1 >= k0) {
                 const int kp = k - 1;
                 if (GEOM == HX_CART) {
-                    const R mu = N::from_d(dtd / w2prev);
+                    const R mu = N::from_d(div_rn(dtd, w2prev));
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += mu * (fzlo[v] - Fz[v]);
@@ -1058,7 +1058,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 } else {
                     const double dph = w2prev;
                     const double dV = g_vrct() * dph;
-                    const R kv = N::from_d(dtd / dV);
+                    const R kv = N::from_d(div_rn(dtd, dV));
                     const R dS = N::from_d(g_hrw());
 #pragma unroll
                     for (int v = 0; v < NV; v++)
@@ -1089,7 +1089,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                     Un[(long long)v * p.plane + off] = acc[v];
                 double sr;
                 if constexpr (sizeof(R) == 4) {
-                    const float rw[3] = {rwx, rwy, (float)(1.0 / (GEOM == HX_CART ? w2prev : g_rsxy() * w2prev))};
+                    const float rw[3] = {rwx, rwy, (float)div_rn(1.0, GEOM == HX_CART ? w2prev : g_rsxy() * w2prev)};
                     sr = cfl_rate_f32<NV, NDIM>(acc, gas, rw);
                 } else {
                     double wd[3] = {wx, wy, GEOM == HX_CART ? w2prev : g_rsxy() * w2prev};
@@ -1139,7 +1139,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             for (int v = 0; v < NV; v++)
                 acc[v] = qcur[v];
             if (GEOM == HX_CART) {
-                const R mu = N::from_d(dtd / wx);
+                const R mu = N::from_d(div_rn(dtd, wx));
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     acc[v] += mu * (Fx[v] - Fxr[v]);
@@ -1152,7 +1152,7 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
                 const double rm = g_rm(), rp = g_rp();
                 dSrm = rm * rm * ctj * dph;
                 dSrp = rp * rp * ctj * dph;
-                const double kvd = dtd / dV;
+                const double kvd = div_rn(dtd, dV);
                 const R kv = N::from_d(kvd);
                 const R sm = N::from_d(dSrm), sp = N::from_d(dSrp);
 #pragma unroll
@@ -1206,14 +1206,14 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
             // y terms of plane k
             if (NDIM >= 2) {
                 if (GEOM == HX_CART) {
-                    const R muy = N::from_d(dtd / wy);
+                    const R muy = N::from_d(div_rn(dtd, wy));
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] += muy * (Fy[v] - Fyu[v]);
                     if constexpr (DE)
                         acc[NV - 1] += muy * (pek * (ufy - ufyu));
                 } else {
-                    const double kvd = dtd / dV;
+                    const double kvd = div_rn(dtd, dV);
                     const R kv = N::from_d(kvd);
                     dStm = g_hrsm() * dph;
                     dStp = g_hrsp() * dph;
