@@ -175,7 +175,7 @@ __device__ __forceinline__ double cfl_rate(const R* acc, double gamma, const dou
         pr = (gamma - 1.0) * (q[4] - ke);
         if (!fin || !(rho > 0.0) || !(pr > 0.0))
             return -1.0;
-        cs = sqrt(gamma * pr * inv);
+        cs = sqrt_rn(gamma * pr * inv);
     }
     const double u[3] = {u1, u2, u3};
     double s = 0.0;
