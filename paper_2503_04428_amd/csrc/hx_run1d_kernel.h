@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(Run1dShape<R>::threads) run1d_kernel(const Run
             // (the tables hold every cell's own slope factors and its image's width)
             const int gx = c + ng;
             const R cmx = N::from_d(p.geo.cm[0][gx]), cpx = N::from_d(p.geo.cp[0][gx]);
-            const R lamx = N::from_d(dtd / (2.0 * p.geo.w[0][gx]));
+            const R lamx = N::from_d(div_rn(dtd, 2.0 * p.geo.w[0][gx]));
             R w[NV], dl[NV], a[NV], b[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(Run1dShape<R>::threads) run1d_kernel(const Run
         for (int m = 0; m < R1_CPT; m++) {
             const int i = tid + R1_THREADS * m;
             if (i < n) {
-                const R mu = N::from_d(dtd / p.geo.w[0][i + ng]);
+                const R mu = N::from_d(div_rn(dtd, p.geo.w[0][i + ng]));
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     U[m][v] += mu * (sW[v * ld + i + 2] - sW[v * ld + i + 3]);
