@@ -2,8 +2,9 @@
 //
 // Conserved state U = (rho, m1, m2, m3, E, rho f_1..), primitives W = (rho, u1, u2, u3, P, f..)
 // (paper Sect. 2.1 and eq. eos_gas).  The FP64 instantiation evaluates every expression in the
-// same order as the FP64 CPU oracle so that the two agree to the last bits; the FP32 form keeps
-// the internal-energy recovery E - |m|^2/(2 rho) in FP64 and uses hardware reciprocal/sqrt.
+// same order as the FP64 CPU oracle so that the two agree to the last bits; the FP32 form
+// recovers the internal energy E - |m|^2/(2 rho) in FP64 where the kinetic energy dominates (high
+// Mach) and uses hardware reciprocal/sqrt.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -246,22 +247,27 @@ struct PrimImpl<double, NV, DE, EOS> {
 template <int NV, bool DE, int EOS>
 struct PrimImpl<float, NV, DE, EOS> {
     static_assert(EOS == 0, "the gas + radiation EoS is built for FP64");
-    // FP32 bulk, FP64 island for the internal energy: 1/rho from the hardware reciprocal refined
-    // by one FP64 Newton step, then e = E - |m|^2/(2 rho) in FP64.
+    // FP32 bulk: 1/rho from the hardware reciprocal refined by one Newton step, the velocities and
+    // e = E - |m|^2/(2 rho) in FP32 where the kinetic energy is at most 3/4 of E (then the
+    // subtraction loses at most two bits); above that (high Mach, where E - e_k cancels) and for
+    // non-physical states, e is recovered in FP64 from the FP32 values (FP64 island).
     static __device__ __forceinline__ float run(const Gas<float>& g, const float* q, float* w, float*)
     {
-        float rho = q[0];
-        float r = __builtin_amdgcn_rcpf(rho);
-        double id = (double)r;
-        id = id * (2.0 - (double)rho * id);
-        double m1 = q[1], m2 = q[2], m3 = q[3];
-        double ke = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * id;
-        float inv = (float)id;
+        const float rho = q[0];
+        const float r = __builtin_amdgcn_rcpf(rho);
+        const float inv = fmaf(r, fmaf(-rho, r, 1.0f), r);
         w[0] = rho;
         w[1] = q[1] * inv;
         w[2] = q[2] * inv;
         w[3] = q[3] * inv;
-        w[4] = (float)((double)g.gm1 * ((double)q[4] - ke));
+        float e = q[4] - 0.5f * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]);
+        if (!(e > 0.25f * q[4])) {
+            double id = (double)r;
+            id = id * (2.0 - (double)rho * id);
+            const double m1 = q[1], m2 = q[2], m3 = q[3];
+            e = (float)((double)q[4] - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * id);
+        }
+        w[4] = g.gm1 * e;
 #pragma unroll
         for (int v = 5; v < NV - DE; v++)
             w[v] = q[v] * inv;
@@ -280,8 +286,8 @@ __device__ __forceinline__ R to_prim(const Gas<R>& g, const R* q, R* w, R* T = n
 }
 
 // CFL signal rate of the FP32 form, sum_d (|u_d| + c_s) rw_d with rw_d the reciprocal widths rounded
-// once to FP32: the internal energy E - |m|^2/(2 rho) is recovered in FP64 (as in to_prim), the
-// rest is FP32; the maximum over cells and the time step cfl / max stay FP64.  A negative value
+// once to FP32: the internal energy E - |m|^2/(2 rho) is recovered in FP64 for every state (the
+// island that to_prim keeps for high Mach), the rest is FP32; the maximum over cells and the time step cfl / max stay FP64.  A negative value
 // marks a non-physical state.  The sweep's store and the standalone CFL kernel both use it, and it
 // is rounded as written whatever the unit's contraction setting, so the time step of a state does
 // not depend on which of them computed it.
@@ -289,8 +295,8 @@ template <int NV, int NDIM>
 __device__ __forceinline__ double cfl_rate_f32(const float* q, const Gas<float>& g, const float* rw)
 {
     // rounded as written whatever the unit's contraction setting: the primitives are the
-    // operations of to_prim<float> (FP64 island for the internal energy), repeated here so that
-    // the FP32 sweeps keep contraction in their own conversions
+    // operations of to_prim<float>'s FP64 island, repeated here so that the FP32 sweeps keep
+    // contraction in their own conversions
 #pragma clang fp contract(off)
     bool fin = true;
 #pragma unroll
@@ -382,9 +388,8 @@ __device__ __forceinline__ R de_alpha(R e, R ek, R eps)
 }
 
 // rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division).  The FP32 form
-// evaluates it in FP64, where the products of its FP32 values are exact: the sign is then the one
-// of the FP64 internal-energy recovery that the Riemann solver applies to the same state, also
-// when the kinetic energy dominates and FP32 arithmetic would cancel.
+// evaluates it in FP64, where the products of its FP32 values are exact: the sign is the exact one
+// for the FP32 state, also when the kinetic energy dominates and FP32 arithmetic would cancel.
 template <typename R>
 __device__ __forceinline__ bool positive_state(const R* q)
 {

@@ -1,5 +1,6 @@
 // FP32-form instantiations of the fused sweep (FP32 storage and bulk arithmetic; FP64 for
-// the internal-energy recovery, the time step and the source terms).
+// the internal-energy recovery at high Mach, the positivity test, the time step and the source
+// terms).
 // HLLC + van Leer, fixed at compile time.
 #include "hx_sweep_inst.h"
 
