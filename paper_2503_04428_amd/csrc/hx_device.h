@@ -388,15 +388,24 @@ __device__ __forceinline__ R de_alpha(R e, R ek, R eps)
 }
 
 // rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division).  The FP32 form
-// evaluates it in FP64, where the products of its FP32 values are exact: the sign is the exact one
-// for the FP32 state, also when the kinetic energy dominates and FP32 arithmetic would cancel.
+// takes the exact sign for the FP32 state, also when the kinetic energy dominates and FP32
+// arithmetic would cancel: it decides in FP32 where the value is farther from zero than the FP32
+// rounding error (at most about 6 u (|2 rho E| + |m|^2), u = 2^-24; tested against 16 u), and
+// otherwise in FP64, where the products of the FP32 values are exact.
 template <typename R>
 __device__ __forceinline__ bool positive_state(const R* q)
 {
     if constexpr (sizeof(R) == 4) {
-        const double r = q[0], m1 = q[1], m2 = q[2], m3 = q[3], e = q[4];
-        const double mm = m1 * m1 + m2 * m2 + m3 * m3;
-        return q[0] > 0.0f && 2.0 * r * e - mm > 0.0;
+        const float a = 2.0f * q[0] * q[4];
+        const float b = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        const float p = a - b;
+        bool pos = p > 0.0f;
+        if (!(fabsf(p) > 0x1p-20f * (fabsf(a) + b))) {
+            const double r = q[0], m1 = q[1], m2 = q[2], m3 = q[3], e = q[4];
+            const double mm = m1 * m1 + m2 * m2 + m3 * m3;
+            pos = 2.0 * r * e - mm > 0.0;
+        }
+        return q[0] > 0.0f && pos;
     } else {
         R m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         return q[0] > R(0) && R(2) * q[0] * q[4] - m2 > R(0);
