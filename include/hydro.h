@@ -204,6 +204,16 @@ hx_status hx_get_time(hx_ctx *ctx, double *t);
  * host; synchronises).  For tests of the enclosed-mass reduction. */
 hx_status hx_enclosed_mass(hx_ctx *ctx, double *h_menc);
 
+/* Check of the FP64 arithmetic the sweeps use (context-free; device pointers; asynchronous on
+ * hip_stream): d_q[i] = d_a[i] / d_b[i] and d_s[i] = sqrt(|d_a[i]|) for n elements, computed with
+ * the sweeps' own division and square root (the hardware reciprocal and reciprocal square root
+ * refined by Newton steps with FMA corrections, without range scaling).  They are the IEEE
+ * round-to-nearest results for operands whose quotients and roots lie well inside the normal range
+ * (exponents within about +-700); zero, infinite and NaN operands are outside their domain.
+ * HX_EINVAL for null pointers or n < 0. */
+hx_status hx_arith_check(const double *d_a, const double *d_b, long long n, double *d_q, double *d_s,
+                         void *hip_stream);
+
 /* ---- learned slope limiter (context-free; device pointers; asynchronous on hip_stream) ----
  * The limiter network maps the four undivided differences of a primitive around a cell,
  * normalised by their largest magnitude, to phi in (0, 2); the limited slope is phi times the

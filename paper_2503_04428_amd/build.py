@@ -13,6 +13,7 @@ Each HIP translation unit is compiled separately (no relocatable device code):
   hx_mlp.hip         learned limiter: BF16-MFMA evaluation, training samples, FP32 training
   hx_run1d_fp64.hip  persistent one-workgroup run of a 1D problem to t_end, -ffp-contract=off
   hx_run1d_fp32.hip  the same for the FP32 form (the FP32 sweep's flags)
+  hx_arith.hip       the sweeps' FP64 division and square root over arrays (checked against IEEE)
   hx_abi.hip         C ABI host code
 Packed FP32 instructions are disabled for all device code.
 """
@@ -50,6 +51,7 @@ UNITS = {
     "hx_mlp.hip": ["-ffp-contract=off"],
     "hx_run1d_fp64.hip": ["-ffp-contract=off"],
     "hx_run1d_fp32.hip": [],
+    "hx_arith.hip": ["-ffp-contract=off"],
     "hx_abi.hip": ["-ffp-contract=off"],
 }
 

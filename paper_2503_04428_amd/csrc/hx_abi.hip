@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "hx_launch.h"
+#include "hx_arith.h"
 #include "hx_run1d.h"
 
 namespace {
@@ -902,6 +903,16 @@ hx_status hx_enclosed_mass(hx_ctx* x, double* h_menc)
     HIPCHECK(hipMemcpyAsync(h_menc, at<double>(x, x->L.menc), sizeof(double) * x->cfg.n[0], hipMemcpyDeviceToHost,
                             x->stream));
     HIPCHECK(hipStreamSynchronize(x->stream));
+    return HX_OK;
+}
+
+hx_status hx_arith_check(const double* d_a, const double* d_b, long long n, double* d_q, double* d_s, void* hip_stream)
+{
+    if (!d_a || !d_b || !d_q || !d_s || n < 0)
+        return fail(HX_EINVAL, "invalid argument");
+    if (n == 0)
+        return HX_OK;
+    HIPCHECK(hx::launch_arith_check(d_a, d_b, n, d_q, d_s, (hipStream_t)hip_stream));
     return HX_OK;
 }
 

@@ -57,7 +57,7 @@ _lib = None
 # names of the exported entry points, as declared in include/hydro.h
 EXPORTS = ["hx_workspace_bytes", "hx_create", "hx_set_state", "hx_get_state", "hx_compute_dt",
            "hx_compute_dt_device", "hx_step", "hx_step_device", "hx_run_1d", "hx_totals", "hx_check", "hx_set_mlp",
-           "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_shift_grid", "hx_enclosed_mass", "hx_mlp_eval", "hx_mlp_features",
+           "hx_set_zchunk", "hx_get_zchunk", "hx_set_time", "hx_get_time", "hx_shift_grid", "hx_enclosed_mass", "hx_arith_check", "hx_mlp_eval", "hx_mlp_features",
            "hx_mlp_grad_workspace_bytes", "hx_mlp_grad", "hx_mlp_grad_noalloc", "hx_mlp_adam", "hx_last_error",
            "hx_destroy"]
 
@@ -91,6 +91,7 @@ def load_library():
     L.hx_shift_grid.argtypes = [vp, C.c_double]
     L.hx_get_time.argtypes = [vp, C.POINTER(C.c_double)]
     L.hx_enclosed_mass.argtypes = [vp, _DP]
+    L.hx_arith_check.argtypes = [vp, vp, C.c_longlong, vp, vp, vp]
     L.hx_mlp_eval.argtypes = [vp, vp, C.c_longlong, vp, vp]
     L.hx_mlp_features.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, vp]
     L.hx_mlp_grad_workspace_bytes.argtypes = [C.c_longlong]
@@ -342,6 +343,21 @@ def _check(L, st):
 
 def _stream_ptr(torch, stream):
     return C.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def arith_check(a, b, stream=None):
+    """The sweeps' FP64 division and square root on device FP64 tensors: (a / b, sqrt(|a|))."""
+    import torch
+
+    L = load_library()
+    a = a.contiguous().double()
+    b = b.contiguous().double()
+    n = a.numel()
+    q = torch.empty_like(a)
+    r = torch.empty_like(a)
+    _check(L, L.hx_arith_check(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_longlong(n),
+                               C.c_void_p(q.data_ptr()), C.c_void_p(r.data_ptr()), _stream_ptr(torch, stream)))
+    return q, r
 
 
 def mlp_eval(w, x, stream=None):
