@@ -557,12 +557,13 @@ __global__ void __launch_bounds__(Tile<NDIM>::BX* Tile<NDIM>::BY, (MinWaves<R, N
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float* qphi = reinterpret_cast<float*>(sQ[wv]);  // phi of slot e at qphi[2 e]
+        // the network's operands, read once for all the tiles of the queue
+        MlpLane m;
+        mlp_lane_from_shared(sMlp, lane, m);
         for (unsigned t0 = 0; t0 < total; t0 += 16) {
             const unsigned e = t0 + (lane & 15);
             // lanes past the queue's end evaluate a copy of its last entry, which is not stored
             const bf16x4_t xb = __builtin_bit_cast(bf16x4_t, sQ[wv][e < total ? e : total - 1]);
-            MlpLane m;
-            mlp_lane_from_shared(sMlp, lane, m);
             const float ph = mlp_tile(m, xb);
             if (lane < 16 && e < total)
                 qphi[2 * e] = ph;
