@@ -412,10 +412,10 @@ def test_run_to_t_end(H):
 
 def test_fp32_form_high_mach_advected_flow(H):
     """FP32 form on a smooth flow advected at Mach ~250 (internal energy 6e-5 of the total): the
-    FP64 energy recovery keeps every pressure positive and the positivity test (evaluated in FP64
-    on the FP32 face states, the same sign as the recovery the Riemann solver applies) takes no
-    cell to first order, as in the FP64 oracle; conserved fields at the FP32-form bar, pressure
-    within the resolution of an FP32 total energy (|dE| / e ~ 6e-8 E / e)."""
+    FP64 energy recovery (taken wherever the kinetic energy dominates) keeps every pressure
+    positive and the positivity test (exact sign for the FP32 face states) takes no cell to first
+    order, as in the FP64 oracle; conserved fields at the FP32-form bar, pressure within the
+    resolution of an FP32 total energy (|dE| / e ~ 6e-8 E / e)."""
     prob = P.random_periodic(n=(20, 18, 16), ndim=3, nscalar=2, seed=41, precision="fp32")
     U0 = prob.U0.copy()
     boost = (240.0, 80.0, 40.0)
@@ -447,3 +447,46 @@ def test_fp32_form_high_mach_advected_flow(H):
     assert np.max(np.abs(pg - po) / po) < 50 * 6e-8 * ratio, np.max(np.abs(pg - po) / po)
     print(f"fp32 high Mach: E/e up to {ratio:.3g}, max relative pressure difference "
           f"{np.max(np.abs(pg - po) / po):.3e}")
+
+
+def test_fp32_form_mixed_mach_shear_flow(H):
+    """FP32 form on a shear flow whose Mach number runs from 0 to about 12 across the grid, so
+    that in the same waves some cells recover the internal energy in FP32 and others (kinetic
+    energy above 3/4 of E) take the FP64 island: conserved fields at the FP32-form bar against the
+    FP64 oracle after 10 steps, every pressure positive and within the resolution of an FP32 total
+    energy of the oracle's."""
+    prob = P.random_periodic(n=(24, 20, 12), ndim=3, nscalar=1, seed=43, precision="fp32")
+    U0 = prob.U0.copy()
+    nz, ny, nx = U0.shape[1:]
+    y = (np.arange(ny) + 0.5) / ny
+    ux = 12.0 * np.sin(2 * np.pi * y)[None, :, None] * np.ones((nz, ny, nx))
+    U0[4] = U0[4] + U0[1] * ux + 0.5 * U0[0] * ux ** 2
+    U0[1] = U0[1] + U0[0] * ux
+    U0 = U0.astype(np.float32).astype(np.float64)
+    prob = prob.with_(U0=U0)
+    ke = 0.5 * (U0[1] ** 2 + U0[2] ** 2 + U0[3] ** 2) / U0[0]
+    island = ke > 0.75 * U0[4]
+    assert island.any() and (~island).any()
+    announce("fp32 form, mixed-Mach shear flow")
+    o = O.Oracle(prob)
+    s = H.Solver(prob, precision="fp32", zchunk=3)
+    s.set_state(U0)
+    U = U0.copy()
+    for _ in range(10):
+        dt, st = o.compute_dt(U)
+        assert st == 0
+        U, st = o.step(U, dt)
+        assert st == 0
+        s.step(dt)
+    G = s.state_numpy()
+    s.check()
+    s.close()
+    assert_parity(G, U, rel=FP32_REL, absf=FP32_ABS, what="fp32 mixed mach", flow_scale=True)
+    pg = 0.4 * (G[4] - 0.5 * (G[1] ** 2 + G[2] ** 2 + G[3] ** 2) / G[0])
+    po = 0.4 * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])
+    ratio = U[4] / (po / 0.4)
+    assert np.all(pg > 0)
+    rel = np.abs(pg - po) / po
+    assert np.all(rel < 50 * 6e-8 * ratio + 1e-4), float(np.max(rel / (50 * 6e-8 * ratio + 1e-4)))
+    print(f"fp32 mixed Mach: {island.mean():.0%} of the cells start in the FP64 island, E/e up to "
+          f"{ratio.max():.3g}, max relative pressure difference {rel.max():.3e}")
