@@ -39,6 +39,12 @@ def assert_parity(Ug: np.ndarray, Uo: np.ndarray, rel: float = 1e-12, absf: floa
             f"{(err / np.maximum(tol, 1e-300))[worst]:.3g} at {worst}")
 
 
+def tol_ratio(Ug, Uo, rel: float = 1e-12, absf: float = 1e-14, flow_scale: bool = False) -> float:
+    """Largest |dU| over its tolerance (1 at the bar)."""
+    tol = parity_tolerance(Uo, rel, absf, flow_scale)
+    return float(np.max(np.abs(Ug - Uo) / np.maximum(tol, 1e-300)))
+
+
 def max_rel(Ug, Uo):
     nv = Uo.shape[0]
     scale = np.abs(Uo).reshape(nv, -1).max(axis=1).reshape((nv,) + (1,) * (Uo.ndim - 1))

@@ -12,7 +12,7 @@ import pytest
 from oracle import oracle as O
 from paper_2503_04428_amd import problems as P
 
-from parity import announce, assert_parity, max_rel
+from parity import announce, assert_parity, max_rel, tol_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +85,12 @@ CASES = {
 }
 
 
+# FP32-form tolerance, from its arithmetic: FP32 rounding (6e-8) through one step of ~10^3 operations
+# per cell, relative to the value, plus a floor for fields that cancel; momenta are floored on the
+# flow's momentum scale (a component that is ~0 everywhere has no scale of its own)
+FP32_REL, FP32_ABS = 2e-5, 2e-6
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_fp64_parity_small(H, name):
     make, nsteps, kz = CASES[name]
@@ -93,6 +99,35 @@ def test_fp64_parity_small(H, name):
     Ug, Uo = run_pair(H, prob, nsteps, zchunk=kz)
     assert_parity(Ug, Uo, what=name)
     print(f"{name}: max relative difference {max_rel(Ug, Uo):.3e}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_form_parity_small(H, name):
+    """The FP32 form on every small case (each dimension, geometry, boundary type, limiter,
+    Riemann solver, gravity mode and field count, so every FP32 instantiation the cases reach),
+    20 steps at most with the oracle's time steps, at the FP32-form bar against the FP64 oracle; its
+    own time step agrees with the oracle's to FP32 rounding."""
+    make, nsteps, kz = CASES[name]
+    prob = make()
+    nsteps = min(nsteps, 20)
+    announce(f"fp32 form parity {name} n={prob.n} nvar={prob.nvar} steps={nsteps} kz={kz}")
+    o = O.Oracle(prob)
+    s = H.Solver(prob, precision="fp32", zchunk=kz)
+    U = prob.U0.copy()
+    s.set_state(U)
+    for n in range(nsteps):
+        dt, st = o.compute_dt(U)
+        assert st == 0
+        if n in (0, nsteps - 1):
+            assert s.compute_dt() == pytest.approx(dt, rel=1e-5), n
+        U, st = o.step(U, dt)
+        assert st == 0
+        s.step(dt)
+    G = s.state_numpy()
+    s.check()
+    s.close()
+    assert_parity(G, U, rel=FP32_REL, absf=FP32_ABS, what=f"fp32 {name}", flow_scale=True)
+    print(f"{name} fp32: largest difference {tol_ratio(G, U, FP32_REL, FP32_ABS, True):.3f} of the bar")
 
 
 def test_fp64_parity_full_size_sedov_sampled(H):
@@ -272,12 +307,6 @@ def _boxes(n, centre, rng, k=5, size=4):
         lo = [int(rng.integers(0, n[d] - size + 1)) for d in range(3)]
         out.append((tuple(lo), tuple(lo[d] + size for d in range(3))))
     return out
-
-
-# FP32-form tolerance, from its arithmetic: FP32 rounding (6e-8) through one step of ~10^3 operations
-# per cell, relative to the value, plus a floor for fields that cancel; momenta are floored on the
-# flow's momentum scale (a component that is ~0 everywhere has no scale of its own)
-FP32_REL, FP32_ABS = 2e-5, 2e-6
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
