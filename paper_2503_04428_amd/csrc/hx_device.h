@@ -388,10 +388,12 @@ __device__ __forceinline__ R de_alpha(R e, R ek, R eps)
 }
 
 // rho > 0 and P > 0, the latter tested as 2 rho E - |m|^2 > 0 (no division).  The FP32 form
-// takes the exact sign for the FP32 state, also when the kinetic energy dominates and FP32
-// arithmetic would cancel: it decides in FP32 where the value is farther from zero than the FP32
-// rounding error (at most about 6 u (|2 rho E| + |m|^2), u = 2^-24; tested against 16 u), and
-// otherwise in FP64, where the products of the FP32 values are exact.
+// decides in FP32 where the computed value is farther from zero than its rounding error can reach
+// (at most about 6 u (|2 rho E| + |m|^2), u = 2^-24, plus the absolute error of subnormal
+// products; tested against 16 u and 2^-100), so that there the sign is the exact one for the FP32
+// state even where the kinetic energy dominates and FP32 arithmetic cancels; otherwise it decides
+// in FP64, where the products of the FP32 values are exact and only the sums round (the decision
+// of an all-FP64 test).
 template <typename R>
 __device__ __forceinline__ bool positive_state(const R* q)
 {
@@ -400,7 +402,7 @@ __device__ __forceinline__ bool positive_state(const R* q)
         const float b = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         const float p = a - b;
         bool pos = p > 0.0f;
-        if (!(fabsf(p) > 0x1p-20f * (fabsf(a) + b))) {
+        if (!(fabsf(p) > fmaf(0x1p-20f, fabsf(a) + b, 0x1p-100f))) {
             const double r = q[0], m1 = q[1], m2 = q[2], m3 = q[3], e = q[4];
             const double mm = m1 * m1 + m2 * m2 + m3 * m3;
             pos = 2.0 * r * e - mm > 0.0;
