@@ -67,6 +67,29 @@ def test_smallest_grids_match_oracle(H, name):
     print(f"{name}: max relative difference {max_rel(Ug, Uo):.3e}")
 
 
+@pytest.mark.parametrize("name", list(SMALL))
+def test_smallest_grids_fp32_form(H, name):
+    """The FP32 form on the same smallest grids, with the oracle's time steps, at the FP32-form bar
+    of the parity tests (2e-5 of the value plus 2e-6 of the field's scale, momenta on the flow's
+    momentum scale)."""
+    prob = P.random_periodic(**SMALL[name])
+    announce(f"smallest grid {name} n={prob.n}, fp32 form")
+    o = O.Oracle(prob)
+    s = H.Solver(prob, precision="fp32", zchunk=1 if prob.ndim == 3 else None)
+    U = prob.U0.copy()
+    s.set_state(U)
+    for _ in range(15):
+        dt, st = o.compute_dt(U)
+        assert st == 0
+        U, st = o.step(U, dt)
+        assert st == 0
+        s.step(dt)
+    Ug = s.state_numpy()
+    s.check()
+    s.close()
+    assert_parity(Ug, U, rel=2e-5, absf=2e-6, what=f"{name} fp32", flow_scale=True)
+
+
 def _uniform(n, ndim, nscalar, precision, limiter="vanleer", ng=2):
     pr = P.random_periodic(n=n, ndim=ndim, nscalar=nscalar, seed=1, amp=0.0, ng=ng, precision=precision,
                            limiter=limiter)
