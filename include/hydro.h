@@ -71,8 +71,9 @@ typedef struct {
     double cfl;             /* Courant number of hx_compute_dt */
     int riemann;            /* HX_RIEMANN_* (Sect. 3.2) */
     int limiter;            /* HX_LIMITER_* (Sect. 3.2) */
-    int precision;          /* HX_PRECISION_*: FP64, or FP32 storage/bulk with FP64 energy
-                               recovery, time step, totals and source terms */
+    int precision;          /* HX_PRECISION_*: FP64, or FP32 storage/bulk with the internal
+                               energy recovered in FP64 where the kinetic energy dominates and
+                               the time step, totals and source terms in FP64 */
     int bc[3][2];           /* HX_BOUNDARY_* per axis, low and high side (Sect. 3.2) */
     int gravity;            /* HX_GRAVITY_*: uniform g0 (Cartesian, eq. uniform_gravity); point mass
                                G*Mc (spherical, eq. point_gravity); point mass plus the enclosed
@@ -152,8 +153,8 @@ hx_status hx_step_device(hx_ctx *ctx, const double *d_dt);
  * max_steps steps, inside one workgroup on the device: the state stays on chip, each step takes
  * the CFL time step and the MUSCL-Hancock step of hx_compute_dt / hx_step (FP64: the same results,
  * bit for bit, as that host loop; FP32 form: the same to FP32 rounding, since the compiler may
- * contract FP32 products and sums differently in the two kernels), and no kernel is launched and nothing synchronises per step (Sect.
- * 3.2; the Sod tube of App. C.1 is this size).  For one Cartesian row (ndim 1, n[1] = 1) of at
+ * contract FP32 products and sums differently in the two kernels), and no kernel is launched and
+ * nothing synchronises per step (Sect. 3.2; the Sod tube of App. C.1 is this size).  For one Cartesian row (ndim 1, n[1] = 1) of at
  * most 2046 cells whose primitives and face states, 3 nvar (n + 4) values of 8 bytes (FP64) or 4
  * (FP32 form), fit the device's LDS with 512 bytes to spare (160 KiB on gfx950: at most 1357 cells
  * with 5 fields in FP64, 2046 in FP32), with the ideal gas and no gravity, heating,
