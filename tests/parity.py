@@ -13,7 +13,7 @@ def announce(msg: str):
 def parity_tolerance(Uo: np.ndarray, rel: float = 1e-12, absf: float = 1e-14, flow_scale: bool = False) -> np.ndarray:
     """Per cell |dU| <= rel |U_oracle| + absf * scale of that field, scale = max_cells |U_oracle|.
     With flow_scale, the three momenta share one scale, at least sqrt(max rho * max E) (the momentum
-    of the flow's energy), so that a momentum that is ~0 everywhere is not judged on its own size."""
+    of the flow's energy), so that a momentum that is ~0 everywhere is not measured against its own size."""
     nv = Uo.shape[0]
     scale = np.abs(Uo).reshape(nv, -1).max(axis=1)
     if flow_scale:
