@@ -309,6 +309,37 @@ def _boxes(n, centre, rng, k=5, size=4):
     return out
 
 
+def test_full_size_sedov_fp32_form_200_steps(H):
+    """The FP32 form on the headline workload (Sedov 256^3 in the benchmark's launch configuration):
+    200 steps with the oracle's time steps against the oracle's boxed run, every cell at the
+    FP32-form bar and each field's L1 within 1e-5 of the oracle's, and the form's own time step
+    within 1e-5 of the oracle's at the first and the last step."""
+    from parity import BoxedRun
+    prob = P.sedov3d(n=256)
+    announce("fp32 form, full-size sedov 256^3, 200 steps, every cell")
+    lib = O.OMP_LIB_PATH if os.path.exists(O.OMP_LIB_PATH) else O.LIB_PATH
+    run = BoxedRun(O.Oracle(prob, library=lib), prob.U0.copy())
+    s = H.Solver(prob, precision="fp32")
+    s.set_state(prob.U0)
+    for n in range(1, 201):
+        dt, st = run.compute_dt()
+        assert st == 0
+        if n in (1, 200):
+            assert s.compute_dt() == pytest.approx(dt, rel=1e-5), n
+        assert run.step(dt) == 0
+        s.step(dt)
+    G = s.state_numpy()
+    s.check()
+    s.close()
+    U = run.U
+    assert_parity(G, U, rel=FP32_REL, absf=FP32_ABS, what="sedov256 fp32 after 200 steps", flow_scale=True)
+    nv = U.shape[0]
+    l1 = np.abs(G - U).reshape(nv, -1).sum(axis=1) / np.abs(U).reshape(nv, -1).sum(axis=1)
+    print(f"sedov 256^3 fp32, 200 steps: L1 relative per field {l1}, largest difference "
+          f"{tol_ratio(G, U, FP32_REL, FP32_ABS, True):.3f} of the bar")
+    assert np.all(l1 < 1e-5)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_full_size_rt_sampled(H, precision):
     prob = P.rt3d()
