@@ -259,13 +259,27 @@ def test_device_dt_loop_equals_host_dt_loop(H):
     assert np.array_equal(a.state_numpy(), b.state_numpy())
 
 
-def test_zchunk_does_not_change_results(H):
+@pytest.mark.parametrize("form", ["fp64", "fp32", "learned"])
+def test_zchunk_does_not_change_results(H, form):
+    """Every form gives the same bits whatever the z planes per workgroup (each cell's arithmetic
+    does not depend on the launch layout)."""
+    kw = dict(limiter="mlp", ng=3) if form == "learned" else {}
     prob = P.random_periodic(n=(18, 17, 29), ndim=3, nscalar=1, seed=9,
-                             bc=[["reflective"] * 2, ["transmissive"] * 2, ["reflective"] * 2])
-    announce("z-chunk invariance")
+                             precision="fp64" if form == "fp64" else "fp32",
+                             bc=[["reflective"] * 2, ["transmissive"] * 2, ["reflective"] * 2], **kw)
+    w = None
+    if form == "learned":
+        from paper_2503_04428_amd import learned
+        try:
+            w = learned.load_weights()
+        except OSError:
+            w = np.random.default_rng(5).normal(scale=0.4, size=O.MLP_NPARAM).astype(np.float32)
+    announce(f"z-chunk invariance, {form}")
     outs = []
     for kz in (1, 3, 29, 64):
         s = H.Solver(prob, zchunk=kz)
+        if w is not None:
+            s.set_mlp(w)
         s.set_state(prob.U0)
         for _ in range(5):
             s.step(2e-3)
