@@ -226,19 +226,37 @@ def test_nonphysical_state_reported(H):
     s.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "learned"])
 def test_checkpoint_resume_bitwise(H, precision):
-    prob = P.random_periodic(n=(23, 19, 17), ndim=3, nscalar=2, seed=3)
-    announce(f"checkpoint/resume {precision}")
-    a = H.Solver(prob, precision=precision)
+    """A state fetched mid-run and loaded into a fresh context continues with the same bits."""
+    learned_form = precision == "learned"
+    prob = P.random_periodic(n=(23, 19, 17), ndim=3, nscalar=2, seed=3,
+                             **(dict(limiter="mlp", ng=3, precision="fp32") if learned_form else {}))
+    w = None
+    if learned_form:
+        from paper_2503_04428_amd import learned
+        try:
+            w = learned.load_weights()
+        except OSError:
+            w = np.random.default_rng(6).normal(scale=0.4, size=O.MLP_NPARAM).astype(np.float32)
+        precision = "fp32"
+    announce(f"checkpoint/resume {precision}{' learned' if learned_form else ''}")
+
+    def solver():
+        x = H.Solver(prob, precision=precision)
+        if w is not None:
+            x.set_mlp(w)
+        return x
+
+    a = solver()
     a.set_state(prob.U0)
     a.advance(10)
     ref = a.state_numpy()
-    b = H.Solver(prob, precision=precision)
+    b = solver()
     b.set_state(prob.U0)
     b.advance(5)
     mid = b.get_state()
-    c = H.Solver(prob, precision=precision)
+    c = solver()
     c.set_state(mid)
     c.advance(5)
     assert np.array_equal(c.state_numpy(), ref)
@@ -246,14 +264,17 @@ def test_checkpoint_resume_bitwise(H, precision):
         x.close()
 
 
-def test_device_dt_loop_equals_host_dt_loop(H):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_device_dt_loop_equals_host_dt_loop(H, precision):
+    """The time step kept on the device (hx_compute_dt_device + hx_step_device) gives the same bits
+    as the host loop of hx_compute_dt + hx_step."""
     prob = P.sedov3d(n=32)
-    announce("device-dt loop")
-    a = H.Solver(prob)
+    announce(f"device-dt loop {precision}")
+    a = H.Solver(prob, precision=precision)
     a.set_state(prob.U0)
     for _ in range(12):
         a.step(a.compute_dt())
-    b = H.Solver(prob)
+    b = H.Solver(prob, precision=precision)
     b.set_state(prob.U0)
     b.advance(12)
     assert np.array_equal(a.state_numpy(), b.state_numpy())
