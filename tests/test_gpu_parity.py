@@ -205,12 +205,15 @@ def test_dt_and_totals_match_oracle(H):
     s.close()
 
 
-def test_nonphysical_state_reported(H):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_nonphysical_state_reported(H, precision):
+    """A negative density is reported by the time step and a NaN by the check after a step, in
+    either form; a fresh valid state clears the report."""
     prob = P.random_periodic(n=(20, 18, 9), ndim=3, nscalar=1)
-    announce("non-physical state report")
+    announce(f"non-physical state report {precision}")
     U = prob.U0.copy()
     U[0, 3, 4, 5] = -1.0
-    s = H.Solver(prob)
+    s = H.Solver(prob, precision=precision)
     s.set_state(U)
     with pytest.raises(H.NonPhysicalState):
         s.compute_dt()
