@@ -185,22 +185,31 @@ def test_fp64_parity_full_size_sedov_200_steps(H):
     s.close()
 
 
-def test_dt_and_totals_match_oracle(H):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dt_and_totals_match_oracle(H, precision):
+    """Time step, conserved totals and enclosed masses against the oracle; the FP32 form's totals
+    and enclosed masses are FP64 sums of its (exactly widened) FP32 state, so they match the
+    oracle's on the FP32-rounded state to FP64 summation order, and its time step matches to FP32
+    rounding."""
     prob = P.random_wedge(nr=21, nth=11, nph=9, nscalar=2, gravity="point_monopole",
                           bc=[["reflective", "transmissive"], ["reflective"] * 2, ["periodic"] * 2])
-    announce("dt/totals/enclosed-mass parity")
+    announce(f"dt/totals/enclosed-mass parity {precision}")
+    U0 = prob.U0 if precision == "fp64" else prob.U0.astype(np.float32).astype(np.float64)
     o = O.Oracle(prob)
-    s = H.Solver(prob)
+    s = H.Solver(prob, precision=precision)
     s.set_state(prob.U0)
-    dt, _ = o.compute_dt(prob.U0)
-    assert s.compute_dt() == dt
+    dt, _ = o.compute_dt(U0)
+    if precision == "fp64":
+        assert s.compute_dt() == dt
+    else:
+        assert s.compute_dt() == pytest.approx(dt, rel=1e-5)
     tg = s.totals()
-    to = o.totals(prob.U0)
+    to = o.totals(U0)
     assert np.allclose(tg, to, rtol=1e-13, atol=0)
     s.step(dt)
     s.check()
     me = s.enclosed_mass()
-    mo = o.enclosed_mass(prob.U0)
+    mo = o.enclosed_mass(U0)
     assert np.allclose(me, mo, rtol=1e-13)
     s.close()
 
